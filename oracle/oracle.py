@@ -1,0 +1,278 @@
+"""Python face of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares no code with the HIP path.
+
+Contents
+  * ctypes access to ``fse_oracle.c`` (FP64 Frequency Selective
+    Extrapolation, Sec. II of the paper): :func:`image`, :func:`block`,
+    :func:`plan`.
+  * :func:`tiling` -- the paper's compact tiling, Algorithm 1 with
+    eqs. (1)-(5), written from the equations in pure Python integers.
+  * :func:`tiles_with_stripe` and :func:`image_tiled` -- the overlapping-tile
+    framework of Sec. III: every tile grown by a stripe of d pixels on each
+    side, processed as an independent image, cropped back to its core and
+    merged.
+  * :func:`dependencies` -- which earlier blocks a block must see finished in
+    raster order (a block reads the pixels of its support window, and writes
+    its own lost pixels).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fse_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+TOPN = 4
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile fse_oracle.c with gcc into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d, i, u8 = ctypes.c_double, ctypes.c_int, ctypes.c_uint8
+        lib.fse_oracle_block.restype = d
+        lib.fse_oracle_block.argtypes = [i, P(d), P(d), P(d), i, d, P(i), P(d), P(d), P(d), P(d), P(i)]
+        lib.fse_oracle_plan.restype = i
+        lib.fse_oracle_plan.argtypes = [P(u8), i, i, P(i), i, P(i), P(i), P(i), i, P(i)]
+        lib.fse_oracle_image.restype = i
+        lib.fse_oracle_image.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(i), P(d), i, P(i), P(d),
+                                         P(i), P(d), P(d)]
+        _lib = lib
+    return _lib
+
+
+def _p(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def block(s, w, K: int, gamma: float, history: bool = False):
+    """Greedy sparse fit of one M x M window (complex or real ``s``, weights
+    ``w``).  Returns dict(W0, sel, alpha (complex K), e_top, i_top[, R])."""
+    lib = _load()
+    s = np.asarray(s)
+    M = s.shape[0]
+    sr = np.ascontiguousarray(s.real, dtype=np.float64)
+    si = np.ascontiguousarray(s.imag, dtype=np.float64) if np.iscomplexobj(s) else None
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    sel = np.zeros(K, np.int32)
+    ar = np.zeros(K)
+    ai = np.zeros(K)
+    et = np.zeros(K * TOPN)
+    it = np.zeros(K * TOPN, np.int32)
+    hist = np.zeros((K + 1) * 2 * M * M) if history else None
+    W0 = lib.fse_oracle_block(M, _p(sr, ctypes.c_double), _p(si, ctypes.c_double), _p(w, ctypes.c_double),
+                              K, gamma, _p(sel, ctypes.c_int), _p(ar, ctypes.c_double),
+                              _p(ai, ctypes.c_double), _p(hist, ctypes.c_double), _p(et, ctypes.c_double),
+                              _p(it, ctypes.c_int))
+    out = {"W0": W0, "sel": sel, "alpha": ar + 1j * ai, "e_top": et.reshape(K, TOPN),
+           "i_top": it.reshape(K, TOPN)}
+    if history:
+        h = hist.reshape(K + 1, 2, M, M)
+        out["R"] = h[:, 0] + 1j * h[:, 1]
+    return out
+
+
+def _classes_arr(classes):
+    return np.ascontiguousarray(np.array(classes, dtype=np.int32).reshape(-1))
+
+
+def plan(mask, classes):
+    """Processing blocks in raster order: arrays (y0, x0, class) and the
+    owner map (block index per lost pixel, -1 elsewhere)."""
+    lib = _load()
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    H, W = mask.shape
+    ca = _classes_arr(classes)
+    n = lib.fse_oracle_plan(_p(mask, ctypes.c_uint8), W, H, _p(ca, ctypes.c_int), len(classes), None, None,
+                            None, 0, None)
+    n = -n if n < 0 else n
+    y = np.zeros(max(n, 1), np.int32)
+    x = np.zeros(max(n, 1), np.int32)
+    c = np.zeros(max(n, 1), np.int32)
+    owner = np.zeros((H, W), np.int32)
+    r = lib.fse_oracle_plan(_p(mask, ctypes.c_uint8), W, H, _p(ca, ctypes.c_int), len(classes), _p(y, ctypes.c_int),
+                            _p(x, ctypes.c_int), _p(c, ctypes.c_int), n, _p(owner, ctypes.c_int))
+    assert r == n
+    return y[:n], x[:n], c[:n], owner
+
+
+def image(img, mask, classes, rho=0.8, gamma=0.5, delta=0.5, order=None, trace=False):
+    """FP64 extrapolation of a whole image.  Returns the output (float64) or,
+    with ``trace=True``, (out, trace dict with sel/e_top/i_top/alpha/W0 per
+    raster block)."""
+    lib = _load()
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    H, W = img.shape
+    assert mask.shape == (H, W)
+    ca = _classes_arr(classes)
+    out = np.zeros((H, W))
+    order_a = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+    Kmax = max(c[2] for c in classes)
+    tr = None
+    if trace:
+        nb, _, _, _ = plan(mask, classes)
+        n = len(nb)
+        tr = {"sel": np.full((n, Kmax), -1, np.int32), "e_top": np.zeros((n, Kmax, TOPN)),
+              "i_top": np.full((n, Kmax, TOPN), -1, np.int32), "alpha": np.zeros((n, Kmax, 2)),
+              "W0": np.zeros(n)}
+    rc = lib.fse_oracle_image(_p(img, ctypes.c_double), _p(mask, ctypes.c_uint8), W, H, _p(ca, ctypes.c_int),
+                              len(classes), rho, gamma, delta, _p(order_a, ctypes.c_int),
+                              _p(out, ctypes.c_double), Kmax,
+                              _p(tr["sel"], ctypes.c_int) if trace else None,
+                              _p(tr["e_top"], ctypes.c_double) if trace else None,
+                              _p(tr["i_top"], ctypes.c_int) if trace else None,
+                              _p(tr["alpha"], ctypes.c_double) if trace else None,
+                              _p(tr["W0"], ctypes.c_double) if trace else None)
+    if rc == -1:
+        raise ValueError("oracle: bad arguments")
+    if trace:
+        tr["alpha"] = tr["alpha"][..., 0] + 1j * tr["alpha"][..., 1]
+        tr["degenerate"] = rc == -2
+        return out, tr
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1: compact tiling (Sec. III, eqs. (1)-(5))
+# ---------------------------------------------------------------------------
+
+def _round_half_up(q: Fraction) -> int:
+    """round() of a non-negative rational, halves rounded up."""
+    return int((q + Fraction(1, 2)) // 1)
+
+
+def tiling(W: int, H: int, N: int):
+    """Tiles (x_T, y_T, w_T, h_T) of a W x H image into N tiles.
+
+    Landscape is assumed (W >= H); otherwise the axes are swapped, tiled and
+    swapped back.  eq. (1) r = W / H; eq. (2) n_R = max(1, round(sqrt(N / r)));
+    eq. (3) n_C per row i (1-based): ceil(N / n_R) for i <= N mod n_R, else
+    floor; eq. (4) h_T = floor(H n_C / N) + floor(((H n_C) mod N) / n_R), the
+    last row taking the rest of the height; eq. (5) w_T per tile j (1-based):
+    ceil(W / n_C) for j <= W mod n_C, else floor.  Offsets accumulate.
+    sqrt(N / r) is rounded exactly: round(sqrt(q)) = k  iff
+    (k - 1/2)^2 <= q < (k + 1/2)^2.
+    """
+    if W < H:
+        return [(y, x, h, w) for (x, y, w, h) in tiling(H, W, N)]
+    r = Fraction(W, H)
+    q = Fraction(N) / r  # value under the square root
+    k = 0
+    while Fraction(2 * k + 1, 2) ** 2 <= q:
+        k += 1
+    n_R = max(1, k)
+    tiles = []
+    y_T = 0
+    for i in range(1, n_R + 1):
+        if i <= N % n_R:
+            n_C = -(-N // n_R)
+        else:
+            n_C = N // n_R
+        h_T = (H * n_C) // N + ((H * n_C) % N) // n_R
+        if i == n_R:
+            h_T = H - y_T
+        x_T = 0
+        for j in range(1, n_C + 1):
+            if j <= W % n_C:
+                w_T = -(-W // n_C)
+            else:
+                w_T = W // n_C
+            tiles.append((x_T, y_T, w_T, h_T))
+            x_T += w_T
+        y_T += h_T
+    return tiles
+
+
+def tiles_with_stripe(W: int, H: int, N: int, d: int, align: int = 1):
+    """Core tiles of :func:`tiling`, optionally with every interior edge moved
+    down to a multiple of ``align`` (block-grid alignment), each grown by the
+    stripe d on all four sides and clipped to the image.  Returns a list of
+    (core, extended) rectangles, each (x, y, w, h)."""
+    out = []
+    for (x, y, w, h) in tiling(W, H, N):
+        x1, y1 = x + w, y + h
+        if align > 1:
+            x0a = (x // align) * align
+            y0a = (y // align) * align
+            x1a = W if x1 == W else (x1 // align) * align
+            y1a = H if y1 == H else (y1 // align) * align
+            x, y, x1, y1 = x0a, y0a, x1a, y1a
+        ex0, ey0 = max(0, x - d), max(0, y - d)
+        ex1, ey1 = min(W, x1 + d), min(H, y1 + d)
+        out.append(((x, y, x1 - x, y1 - y), (ex0, ey0, ex1 - ex0, ey1 - ey0)))
+    return out
+
+
+def image_tiled(img, mask, classes, N: int, d: int, align: int, rho=0.8, gamma=0.5, delta=0.5):
+    """Overlapping-tile framework on the CPU: each extended tile is extrapolated
+    as an independent image, cropped to its core and merged (Sec. III)."""
+    H, W = img.shape
+    out = np.zeros((H, W))
+    for (core, ext) in tiles_with_stripe(W, H, N, d, align):
+        ex, ey, ew, eh = ext
+        if ew <= 0 or eh <= 0:
+            continue
+        sub = image(img[ey:ey + eh, ex:ex + ew], mask[ey:ey + eh, ex:ex + ew], classes, rho, gamma, delta)
+        cx, cy, cw, ch = core
+        out[cy:cy + ch, cx:cx + cw] = sub[cy - ey:cy - ey + ch, cx - ex:cx - ex + cw]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Raster-order dependencies
+# ---------------------------------------------------------------------------
+
+def dependencies(mask, classes):
+    """For every raster block j, the earlier blocks i < j that must be finished
+    before j starts so that j sees the same window as in raster order: i owns
+    a lost pixel inside j's support window (j reads it as reconstructed), or j
+    owns a lost pixel inside i's window (i must read it before j writes it).
+    Brute force over pixels; meant for small images."""
+    y, x, c, owner = plan(mask, classes)
+    H, W = mask.shape
+    n = len(y)
+    win_owners = []
+    for j in range(n):
+        B, b, _ = classes[c[j]]
+        M = B + 2 * b
+        y0, x0 = y[j] - b, x[j] - b
+        sub = owner[max(0, y0):min(H, y0 + M), max(0, x0):min(W, x0 + M)]
+        win_owners.append(set(int(v) for v in np.unique(sub) if v >= 0 and v != j))
+    preds = [set() for _ in range(n)]
+    for j in range(n):
+        for i in win_owners[j]:
+            a, bb = (i, j) if i < j else (j, i)
+            preds[bb].add(a)
+    return [sorted(p) for p in preds]
+
+
+def levels(preds):
+    """Longest-path level of every block (sources at level 0)."""
+    lv = np.zeros(len(preds), np.int64)
+    for j in range(len(preds)):
+        if preds[j]:
+            lv[j] = 1 + max(lv[i] for i in preds[j])
+    return lv

@@ -1,0 +1,201 @@
+/*
+ * fse.h -- C ABI of the MI355X (gfx950) Frequency Selective Extrapolation
+ * library, libfse.so.
+ *
+ * Frequency Selective Extrapolation (FSE) replaces the lost pixels of an image
+ * block by block: each processing block fits a sparse weighted superposition
+ * of 2-D DFT basis functions to the known and already reconstructed pixels of
+ * a support window around it, greedily, K basis functions at a time, and
+ * writes the model into its lost pixels (Sec. II).  The library also provides
+ * the paper's overlapping-tile framework (Sec. III): the compact tiling of
+ * Algorithm 1 (eqs. (1)-(5)), tiles grown by a stripe of d pixels, processed
+ * independently, cropped and merged.
+ *
+ * Conventions
+ *  - Every call returns fse_status_t: FSE_OK (0) or a negative error code;
+ *    fse_status_string() names it.  No C++ exception crosses the ABI.
+ *  - Image, mask and output buffers are DEVICE pointers owned by the caller;
+ *    they must stay valid until the work enqueued on `stream` (or the served
+ *    request) has completed.  `stream` is a hipStream_t passed as void*
+ *    (NULL = the null stream).
+ *  - Images are float32, masks uint8 (1 = lost, 0 = known), row-major with a
+ *    pitch counted in elements.  Values of the input at lost pixels are never
+ *    read (they may be NaN).  The output receives the input at known pixels
+ *    and the extrapolated value at lost pixels; it must not alias the input.
+ *  - The library owns its device workspace (planning tables, per-pixel
+ *    status, an FP64 copy of reconstructed values, scheduling counters).  It
+ *    grows on demand and is kept per stream until fse_release() or exit.
+ *  - A fault of the device surfaces as FSE_ERR_DEVICE on the call that
+ *    observes it.
+ *  - Calls are thread-safe.
+ */
+#ifndef FSE_H
+#define FSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fse_status_t;
+
+#define FSE_OK 0
+#define FSE_ERR_INVALID_ARG (-1)
+#define FSE_ERR_UNSUPPORTED (-2)
+#define FSE_ERR_BUDGET (-3)
+#define FSE_ERR_OUT_OF_MEMORY (-4)
+#define FSE_ERR_DEVICE (-5)
+#define FSE_ERR_TIMEOUT (-6)
+#define FSE_ERR_NOT_FOUND (-7)
+#define FSE_ERR_BUSY (-8)
+
+/* arithmetic of the DFT and of the selection loop */
+#define FSE_PREC_F64 0   /* FP64 MFMA DFT, FP64 loop, FP64 reconstructed values */
+#define FSE_PREC_F32 1   /* FP32 MFMA DFT, FP32 loop (FP64 W0 and coefficients) */
+#define FSE_PREC_BF16X3 2 /* BF16x3 split MFMA DFT with FP32 accumulate, FP32 loop */
+
+/* how the processing blocks of one call are executed */
+#define FSE_SCHED_PERSISTENT 0 /* one persistent launch, device-side dependency waits */
+#define FSE_SCHED_WAVEFRONT 1  /* one launch per wavefront key (host-synchronised) */
+#define FSE_SCHED_PER_BLOCK 2  /* one launch per block in raster order (plain path) */
+
+/* whole image with exact raster semantics, or the paper's tile framework */
+#define FSE_WHOLE 0
+#define FSE_TILED 1
+
+#define FSE_MAX_CLASSES 3
+
+/* A device image: float32 values, `pitch` elements between rows. */
+typedef struct {
+    float* data;
+    int32_t width, height;
+    int64_t pitch;
+} fse_image_t;
+
+/* A device loss mask: uint8, 1 = lost, 0 = known. */
+typedef struct {
+    const uint8_t* data;
+    int32_t width, height;
+    int64_t pitch;
+} fse_mask_t;
+
+/* One tile of Algorithm 1: core rectangle (x, y, w, h) and the core grown by
+ * the stripe d on every side, clipped to the image (ox, oy, ow, oh). */
+typedef struct {
+    int32_t x, y, w, h;
+    int32_t ox, oy, ow, oh;
+} fse_tile_t;
+
+/* A processing-block class: block edge B, support border b (window and DFT
+ * size M = B + 2b), number of selection steps K. */
+typedef struct {
+    int32_t block, border, iters;
+} fse_class_t;
+
+/*
+ * Parameters.  classes[0..n_classes-1] are ordered by decreasing block edge,
+ * each edge a multiple of the next; every class but the last takes aligned
+ * squares that are entirely lost, the last class takes the aligned cells
+ * that still hold a lost pixel.  Supported windows: M = 32 and M = 64.
+ * rho in (0,1]: isotropic weight decay rho^distance; recon_weight in (0,1]:
+ * extra factor for pixels reconstructed by earlier blocks; gamma in (0,2):
+ * orthogonality-deficiency compensation.
+ * trace_sel (device, may be NULL): receives the selected index u*M+v of
+ * every step of every block, at [raster_block_index * trace_stride + step];
+ * trace_capacity bounds the number of blocks traced.
+ */
+typedef struct {
+    int32_t n_classes;
+    fse_class_t classes[FSE_MAX_CLASSES];
+    double rho, gamma, recon_weight;
+    int32_t precision; /* FSE_PREC_* */
+    int32_t schedule;  /* FSE_SCHED_* */
+    int32_t tiling;    /* FSE_WHOLE or FSE_TILED */
+    int32_t n_tiles, overlap, align; /* FSE_TILED: tiles N, stripe d, grid alignment */
+    int32_t workgroups;              /* persistent grid size; 0 = automatic */
+    int32_t* trace_sel;
+    int32_t trace_stride;
+    int64_t trace_capacity;
+} fse_params_t;
+
+/* Counters of the last fse_extrapolate* call on the calling thread. */
+typedef struct {
+    int64_t n_blocks;     /* processing blocks executed (tiles: summed over tiles) */
+    int64_t n_lost_pixels;
+    int64_t n_degenerate; /* blocks whose window held no usable pixel (W0 = 0) */
+    int64_t n_jobs;       /* images x tiles */
+    int32_t wavefront_keys;
+    double host_plan_ms;  /* host-side planning time */
+} fse_run_stats_t;
+
+const char* fse_status_string(fse_status_t s);
+
+/* Default parameters: one class B=4, b=14 (32x32 window and DFT), K=100,
+ * rho=0.8, gamma=0.5, recon_weight=0.5, FP64, persistent schedule, whole image. */
+fse_status_t fse_params_default(fse_params_t* p);
+
+/*
+ * Compact tiling, Algorithm 1 with eqs. (1)-(5) of Sec. III, plus the stripe
+ * d of Sec. III.  tiles: caller-owned host array of N entries.  align > 1
+ * moves every interior tile edge down to a multiple of align (the block grid)
+ * so that the blocks of a tile coincide with those of the image.
+ * Errors: INVALID_ARG when W, H, N < 1, d < 0, align < 1 or N > W*H.
+ */
+fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align,
+                            fse_tile_t* tiles);
+
+/*
+ * Extrapolate the lost pixels of one image (Sec. II; with p->tiling ==
+ * FSE_TILED through the tile framework of Sec. III).  Enqueued on `stream`;
+ * returns once the work is enqueued (the planner reads the mask back to the
+ * host first, so the call waits for the mask to be ready).
+ * Errors: INVALID_ARG (null pointers, size mismatch, parameter ranges),
+ * UNSUPPORTED (window size not 32 or 64), OUT_OF_MEMORY, DEVICE.
+ */
+fse_status_t fse_extrapolate(const fse_image_t* image, const fse_mask_t* mask, const fse_params_t* p,
+                             fse_image_t* out, void* stream);
+
+/* Same for n images in one batched persistent launch (blocks of all images
+ * and tiles share the device queue).  Arrays of n entries. */
+fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
+                                   const fse_params_t* p, fse_image_t* outs, void* stream);
+
+/* Statistics of the last extrapolate call made by this thread. */
+fse_status_t fse_last_stats(fse_run_stats_t* st);
+
+/* Free all cached device workspace (waits for the streams that use it). */
+fse_status_t fse_release(void);
+
+/* ---- serving: continuous batching of requests ------------------------- */
+
+typedef struct fse_server fse_server_t;
+
+typedef struct {
+    int64_t hbm_budget_bytes; /* device memory the server may hold for requests */
+    int32_t max_slots;        /* requests resident at once */
+    int32_t device;           /* HIP device ordinal */
+    int32_t workgroups;       /* persistent grid size, 0 = automatic */
+} fse_serve_config_t;
+
+typedef struct {
+    double t_submit_ms, t_admit_ms, t_done_ms; /* host steady clock */
+    int64_t n_blocks;
+} fse_request_stats_t;
+
+fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** server);
+/* Queue a request.  The buffers are device pointers owned by the caller and
+ * must stay valid until the request is done.  BUDGET when the request can
+ * never fit the budget. */
+fse_status_t fse_serve_submit(fse_server_t* s, const fse_image_t* image, const fse_mask_t* mask,
+                              const fse_params_t* p, fse_image_t* out, uint64_t* ticket);
+fse_status_t fse_serve_poll(fse_server_t* s, uint64_t ticket, int32_t* done, fse_request_stats_t* st);
+/* timeout_us < 0 waits without limit; TIMEOUT when it expires. */
+fse_status_t fse_serve_wait(fse_server_t* s, uint64_t ticket, int64_t timeout_us, fse_request_stats_t* st);
+fse_status_t fse_serve_destroy(fse_server_t* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSE_H */

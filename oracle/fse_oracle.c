@@ -299,6 +299,61 @@ int fse_oracle_plan(const unsigned char* mask, int W, int H, const int* classes,
 }
 
 /*
+ * Support window of one block from an image state: status per pixel
+ * (0 known, 1 lost, 2 reconstructed) and the current values.  Off-image
+ * pixels carry no weight.  w and s are M*M.
+ */
+static void window_of(const double* val, const unsigned char* status, int W, int H, int wy, int wx, int M,
+                      double rho, double delta, double* w, double* s) {
+    double ctr = 0.5 * (double)(M - 1);
+    for (int m = 0; m < M; ++m)
+        for (int n = 0; n < M; ++n) {
+            int y = wy + m, x = wx + n;
+            int st = (y < 0 || y >= H || x < 0 || x >= W) ? ST_OUT : status[(size_t)y * W + x];
+            double dist = sqrt((m - ctr) * (m - ctr) + (n - ctr) * (n - ctr));
+            double wt = 0.0;
+            if (st == ST_KNOWN) wt = pow(rho, dist);
+            else if (st == ST_RECON) wt = delta * pow(rho, dist);
+            w[m * M + n] = wt;
+            s[m * M + n] = wt > 0.0 ? val[(size_t)y * W + x] : 0.0;
+        }
+}
+
+/*
+ * One block in isolation: the block of edge B with top-left (y0, x0) and
+ * border b is extrapolated from the given image state (val, status as in
+ * window_of).  out_vals[B*B] receives Re of the model at every pixel of the
+ * block (row-major, pixels outside the image left untouched); sel[K] (may be
+ * NULL) the chosen indices.  Returns W0.
+ */
+double fse_oracle_one_block(const double* val, const unsigned char* status, int W, int H, int y0, int x0,
+                            int B, int b, int K, double rho, double gamma, double delta, double* out_vals,
+                            int* sel_out) {
+    int M = B + 2 * b;
+    double* w = (double*)calloc((size_t)M * M, sizeof(double));
+    double* s = (double*)calloc((size_t)M * M, sizeof(double));
+    int* sel = (int*)malloc(sizeof(int) * (K > 0 ? K : 1));
+    double* ar = (double*)malloc(sizeof(double) * (K > 0 ? K : 1));
+    double* ai = (double*)malloc(sizeof(double) * (K > 0 ? K : 1));
+    window_of(val, status, W, H, y0 - b, x0 - b, M, rho, delta, w, s);
+    double W0 = fse_oracle_block(M, s, NULL, w, K, gamma, sel, ar, ai, NULL, NULL, NULL);
+    for (int py = 0; py < B; ++py)
+        for (int px = 0; px < B; ++px) {
+            double gr = 0.0, gi = 0.0;
+            if (W0 > 0.0) synth_at(M, K, sel, ar, ai, b + py, b + px, &gr, &gi);
+            out_vals[py * B + px] = gr;
+        }
+    if (sel_out)
+        for (int it = 0; it < K; ++it) sel_out[it] = W0 > 0.0 ? sel[it] : -1;
+    free(w);
+    free(s);
+    free(sel);
+    free(ar);
+    free(ai);
+    return W0;
+}
+
+/*
  * Whole image.  img: H*W values (row-major).  mask: 1 = lost.  out: H*W,
  * receives img with every lost pixel replaced.  order (may be NULL): a
  * permutation of 0..n_blocks-1 giving the processing order by raster index.
@@ -334,20 +389,9 @@ int fse_oracle_image(const double* img, const unsigned char* mask, int W, int H,
         int B = classes[3 * c], b = classes[3 * c + 1], K = classes[3 * c + 2];
         int M = B + 2 * b;
         int wy = blk_y[bi] - b, wx = blk_x[bi] - b;
-        double ctr = 0.5 * (double)(M - 1);
         double* w = (double*)calloc((size_t)M * M, sizeof(double));
         double* s = (double*)calloc((size_t)M * M, sizeof(double));
-        for (int m = 0; m < M; ++m)
-            for (int n = 0; n < M; ++n) {
-                int y = wy + m, x = wx + n;
-                int st = (y < 0 || y >= H || x < 0 || x >= W) ? ST_OUT : status[(size_t)y * W + x];
-                double dist = sqrt((m - ctr) * (m - ctr) + (n - ctr) * (n - ctr));
-                double wt = 0.0;
-                if (st == ST_KNOWN) wt = pow(rho, dist);
-                else if (st == ST_RECON) wt = delta * pow(rho, dist);
-                w[m * M + n] = wt;
-                s[m * M + n] = wt > 0.0 ? out[(size_t)y * W + x] : 0.0;
-            }
+        window_of(out, status, W, H, wy, wx, M, rho, delta, w, s);
         int* sel = (int*)malloc(sizeof(int) * K);
         double* ar = (double*)malloc(sizeof(double) * K);
         double* ai = (double*)malloc(sizeof(double) * K);

@@ -54,6 +54,8 @@ def _load():
         lib.fse_oracle_block.argtypes = [i, P(d), P(d), P(d), i, d, P(i), P(d), P(d), P(d), P(d), P(i)]
         lib.fse_oracle_plan.restype = i
         lib.fse_oracle_plan.argtypes = [P(u8), i, i, P(i), i, P(i), P(i), P(i), i, P(i)]
+        lib.fse_oracle_one_block.restype = d
+        lib.fse_oracle_one_block.argtypes = [P(d), P(u8), i, i, i, i, i, i, i, d, d, d, P(d), P(i)]
         lib.fse_oracle_image.restype = i
         lib.fse_oracle_image.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(i), P(d), i, P(i), P(d),
                                          P(i), P(d), P(d)]
@@ -92,6 +94,21 @@ def block(s, w, K: int, gamma: float, history: bool = False):
         h = hist.reshape(K + 1, 2, M, M)
         out["R"] = h[:, 0] + 1j * h[:, 1]
     return out
+
+
+def one_block(val, status, y0, x0, B, b, K, rho=0.8, gamma=0.5, delta=0.5):
+    """Extrapolate one block from a given image state: ``val`` (H, W) values,
+    ``status`` (H, W) uint8 with 0 known, 1 lost, 2 reconstructed.  Returns
+    (values of the model at the B x B block pixels, selected indices, W0)."""
+    lib = _load()
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    status = np.ascontiguousarray(status, dtype=np.uint8)
+    H, W = val.shape
+    outv = np.zeros(B * B)
+    sel = np.zeros(max(K, 1), np.int32)
+    W0 = lib.fse_oracle_one_block(_p(val, ctypes.c_double), _p(status, ctypes.c_uint8), W, H, y0, x0, B, b, K,
+                                  rho, gamma, delta, _p(outv, ctypes.c_double), _p(sel, ctypes.c_int))
+    return outv.reshape(B, B), sel[:K], W0
 
 
 def _classes_arr(classes):

@@ -1,0 +1,482 @@
+// fse_api.cpp -- the C ABI of libfse: argument checks, workspace, planning
+// and launches.  See include/fse.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "../../include/fse.h"
+#include "fse_internal.h"
+#include "fse_plan.h"
+#include "fse_runtime.h"
+
+namespace fse {
+
+thread_local fse_run_stats_t g_last_stats{};
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+fse_status_t from_hip(hipError_t e) {
+    if (e == hipSuccess) return FSE_OK;
+    if (e == hipErrorOutOfMemory) return FSE_ERR_OUT_OF_MEMORY;
+    return FSE_ERR_DEVICE;
+}
+
+hipError_t DevBuf::ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) {
+        hipError_t e = hipFree(p);
+        if (e != hipSuccess) return e;
+        p = nullptr;
+        cap = 0;
+    }
+    size_t want = std::max<size_t>(n, 256);
+    want = want + want / 4;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = want;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces: one per (device, stream); calls on one stream are serialised
+// ---------------------------------------------------------------------------
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace* workspace_for(hipStream_t st) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto& slot = g_ws[{dev, st}];
+    if (!slot) slot.reset(new Workspace());
+    return slot.get();
+}
+
+void release_all_workspaces() {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto& kv : g_ws) {
+        std::lock_guard<std::mutex> wl(kv.second->mu);
+        hipStreamSynchronize(kv.first.second);
+        kv.second->free_all();
+    }
+    g_ws.clear();
+}
+
+void Workspace::free_all() {
+    for (DevBuf* b : {&recon, &status, &owner, &desc, &lbox, &done, &tickets, &jobs, &misc, &tabs}) b->release();
+    tab_key.clear();
+}
+
+// ---------------------------------------------------------------------------
+// parameter checks
+// ---------------------------------------------------------------------------
+fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
+    if (!p) return FSE_ERR_INVALID_ARG;
+    if (p->n_classes < 1 || p->n_classes > FSE_MAX_CLASSES) return FSE_ERR_INVALID_ARG;
+    if (!(p->rho > 0.0 && p->rho <= 1.0)) return FSE_ERR_INVALID_ARG;
+    if (!(p->gamma > 0.0 && p->gamma < 2.0)) return FSE_ERR_INVALID_ARG;
+    if (!(p->recon_weight > 0.0 && p->recon_weight <= 1.0)) return FSE_ERR_INVALID_ARG;
+    if (p->precision != FSE_PREC_F64) return FSE_ERR_UNSUPPORTED;
+    if (p->schedule < FSE_SCHED_PERSISTENT || p->schedule > FSE_SCHED_PER_BLOCK) return FSE_ERR_INVALID_ARG;
+    if (p->tiling != FSE_WHOLE && p->tiling != FSE_TILED) return FSE_ERR_INVALID_ARG;
+    cls.clear();
+    for (int c = 0; c < p->n_classes; ++c) {
+        const fse_class_t& k = p->classes[c];
+        if (k.block < 1 || k.border < 0 || k.iters < 0 || k.iters > 256) return FSE_ERR_INVALID_ARG;
+        const int M = k.block + 2 * k.border;
+        if (M != 32) return FSE_ERR_UNSUPPORTED;
+        if (k.block * k.block > kThreads || (kThreads % (k.block * k.block)) != 0) return FSE_ERR_UNSUPPORTED;
+        cls.push_back({k.block, k.border, k.iters, M});
+    }
+    for (int c = 0; c + 1 < p->n_classes; ++c)
+        if (cls[c].B <= cls[c + 1].B || cls[c].B % cls[c + 1].B) return FSE_ERR_INVALID_ARG;
+    if (p->tiling == FSE_TILED) {
+        if (p->n_tiles < 1 || p->overlap < 0 || p->align < 1) return FSE_ERR_INVALID_ARG;
+        if (p->align % cls.back().B != 0 || p->overlap % p->align != 0) return FSE_ERR_INVALID_ARG;
+        if (p->align % cls.front().B != 0) return FSE_ERR_INVALID_ARG;
+    }
+    if (p->trace_sel) {
+        int kmax = 0;
+        for (auto& c : cls) kmax = std::max(kmax, c.K);
+        if (p->trace_stride < kmax || p->trace_stride < 1 || p->trace_capacity < 0) return FSE_ERR_INVALID_ARG;
+    }
+    return FSE_OK;
+}
+
+static fse_status_t check_image(const fse_image_t* im) {
+    if (!im || !im->data || im->width < 1 || im->height < 1 || im->pitch < im->width) return FSE_ERR_INVALID_ARG;
+    return FSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device tables: rho^dist per class, twiddles
+// ---------------------------------------------------------------------------
+static fse_status_t upload_tables(Workspace& ws, const std::vector<ClassCfg>& cls, double rho, hipStream_t st,
+                                  LaunchArgs& a) {
+    std::vector<double> key{rho};
+    for (auto& c : cls) key.insert(key.end(), {(double)c.B, (double)c.b});
+    size_t total = 64 + 128;
+    for (auto& c : cls) total += (size_t)c.M * c.M;
+    if (ws.tab_key != key) {
+        std::vector<double> h(total);
+        for (int p = 0; p < 32; ++p) {
+            h[p] = std::cos(2.0 * M_PI * p / 32.0);
+            h[32 + p] = std::sin(2.0 * M_PI * p / 32.0);
+        }
+        for (int p = 0; p < 64; ++p) {
+            h[64 + p] = std::cos(2.0 * M_PI * p / 64.0);
+            h[128 + p] = std::sin(2.0 * M_PI * p / 64.0);
+        }
+        size_t off = 192;
+        for (auto& c : cls) {
+            const double ctr = 0.5 * (c.M - 1);
+            for (int m = 0; m < c.M; ++m)
+                for (int n = 0; n < c.M; ++n)
+                    h[off + m * c.M + n] = std::pow(rho, std::sqrt((m - ctr) * (m - ctr) + (n - ctr) * (n - ctr)));
+            off += (size_t)c.M * c.M;
+        }
+        hipError_t e = ws.tabs.ensure(total * sizeof(double));
+        if (e != hipSuccess) return from_hip(e);
+        e = hipMemcpyAsync(ws.tabs.p, h.data(), total * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return from_hip(e);
+        ws.tab_key = key;
+    }
+    const double* base = (const double*)ws.tabs.p;
+    a.tw32 = base;
+    a.tw64 = base + 64;
+    size_t off = 192;
+    for (size_t c = 0; c < cls.size(); ++c) {
+        a.cls[c].B = cls[c].B;
+        a.cls[c].b = cls[c].b;
+        a.cls[c].M = cls[c].M;
+        a.cls[c].K = cls[c].K;
+        a.cls[c].wtab = base + off;
+        off += (size_t)cls[c].M * cls[c].M;
+    }
+    a.n_classes = (int)cls.size();
+    return FSE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the extrapolation call
+// ---------------------------------------------------------------------------
+struct HostJob {
+    int img;             // index of the image in the batch
+    int ox, oy, W, H;    // region
+    int cx0, cy0, cx1, cy1;
+    RegionPlan plan;
+};
+
+fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                       fse_image_t* outs, hipStream_t st) {
+    fse_run_stats_t stats{};
+    if (n < 1 || !images || !masks || !outs) return FSE_ERR_INVALID_ARG;
+    std::vector<ClassCfg> cls;
+    fse_status_t s = check_params(p, cls);
+    if (s != FSE_OK) return s;
+    for (int i = 0; i < n; ++i) {
+        if (check_image(&images[i]) != FSE_OK || check_image(&outs[i]) != FSE_OK) return FSE_ERR_INVALID_ARG;
+        const fse_mask_t& m = masks[i];
+        if (!m.data || m.width != images[i].width || m.height != images[i].height || m.pitch < m.width)
+            return FSE_ERR_INVALID_ARG;
+        if (outs[i].width != images[i].width || outs[i].height != images[i].height) return FSE_ERR_INVALID_ARG;
+        if (outs[i].data == images[i].data) return FSE_ERR_INVALID_ARG;
+    }
+    Workspace* wsp = workspace_for(st);
+    std::lock_guard<std::mutex> lk(wsp->mu);
+    Workspace& ws = *wsp;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return from_hip(e);
+
+    const double t0 = now_ms();
+    // ---- masks to the host, regions, plans ---------------------------------
+    std::vector<HostJob> jobs;
+    std::vector<std::vector<uint8_t>> hmask(n);
+    for (int i = 0; i < n; ++i) {
+        const int W = images[i].width, H = images[i].height;
+        hmask[i].resize((size_t)W * H);
+        e = hipMemcpy2DAsync(hmask[i].data(), W, masks[i].data, masks[i].pitch, W, H, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return from_hip(e);
+    for (int i = 0; i < n; ++i) {
+        const int W = images[i].width, H = images[i].height;
+        if (p->tiling == FSE_WHOLE) {
+            HostJob J{i, 0, 0, W, H, 0, 0, W, H, {}};
+            jobs.push_back(std::move(J));
+        } else {
+            std::vector<fse_tile_t> tiles(p->n_tiles);
+            s = fse_plan_tiles(W, H, p->n_tiles, p->overlap, p->align, tiles.data());
+            if (s != FSE_OK) return s;
+            for (auto& T : tiles) {
+                if (T.w <= 0 || T.h <= 0) continue;
+                HostJob J{i, T.ox, T.oy, T.ow, T.oh, T.x - T.ox, T.y - T.oy, T.x - T.ox + T.w, T.y - T.oy + T.h, {}};
+                jobs.push_back(std::move(J));
+            }
+        }
+    }
+    for (auto& J : jobs) {
+        const uint8_t* mk = hmask[J.img].data() + (size_t)J.oy * images[J.img].width + J.ox;
+        if (!plan_region(mk, images[J.img].width, J.W, J.H, cls, J.plan)) return FSE_ERR_INVALID_ARG;
+        stats.n_blocks += (int64_t)(J.plan.desc.size() / 4);
+    }
+    for (int i = 0; i < n; ++i)
+        for (uint8_t v : hmask[i]) stats.n_lost_pixels += v != 0;
+    stats.n_jobs = (int64_t)jobs.size();
+
+    // ---- tickets: all blocks of all jobs ordered by wavefront key -----------
+    int max_key = 0;
+    for (auto& J : jobs)
+        for (int k : J.plan.key) max_key = std::max(max_key, k);
+    std::vector<int32_t> kcount(max_key + 2, 0);
+    for (auto& J : jobs)
+        for (int k : J.plan.key) kcount[k + 1]++;
+    for (int k = 0; k <= max_key; ++k) kcount[k + 1] += kcount[k];
+    std::vector<int32_t> kstart(kcount.begin(), kcount.end());
+    const int64_t ntk = stats.n_blocks;
+    std::vector<int32_t> tickets(2 * std::max<int64_t>(ntk, 1));
+    for (size_t j = 0; j < jobs.size(); ++j)
+        for (size_t b = 0; b < jobs[j].plan.key.size(); ++b) {
+            const int pos = kcount[jobs[j].plan.key[b]]++;
+            tickets[2 * pos] = (int32_t)j;
+            tickets[2 * pos + 1] = (int32_t)b;
+        }
+    int nkeys = 0;
+    for (int k = 0; k <= max_key; ++k) nkeys += kstart[k + 1] > kstart[k];
+    stats.wavefront_keys = nkeys;
+
+    // ---- device buffers -----------------------------------------------------
+    size_t n_pix = 0, n_cells = 0, n_blk = 0;
+    for (auto& J : jobs) {
+        n_pix += (size_t)J.W * J.H;
+        n_cells += J.plan.owner.size();
+        n_blk += J.plan.desc.size() / 4;
+    }
+    if ((e = ws.recon.ensure(n_pix * sizeof(double))) != hipSuccess) return from_hip(e);
+    if ((e = ws.status.ensure(n_pix)) != hipSuccess) return from_hip(e);
+    if ((e = ws.owner.ensure(std::max<size_t>(n_cells, 1) * 4)) != hipSuccess) return from_hip(e);
+    if ((e = ws.desc.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
+    if ((e = ws.lbox.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
+    if ((e = ws.done.ensure(std::max<size_t>(n_blk, 1) * 4)) != hipSuccess) return from_hip(e);
+    if ((e = ws.tickets.ensure(tickets.size() * 4)) != hipSuccess) return from_hip(e);
+    if ((e = ws.jobs.ensure(jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
+    if ((e = ws.misc.ensure(64)) != hipSuccess) return from_hip(e);
+
+    // host images of the tables, one upload each
+    std::vector<int32_t> h_owner(std::max<size_t>(n_cells, 1)), h_desc(std::max<size_t>(n_blk, 1) * 4),
+        h_lbox(std::max<size_t>(n_blk, 1) * 4);
+    std::vector<JobDev> h_jobs(jobs.size());
+    size_t o_pix = 0, o_cell = 0, o_blk = 0;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        const HostJob& J = jobs[j];
+        const size_t nb = J.plan.desc.size() / 4;
+        std::copy(J.plan.owner.begin(), J.plan.owner.end(), h_owner.begin() + o_cell);
+        std::copy(J.plan.desc.begin(), J.plan.desc.end(), h_desc.begin() + 4 * o_blk);
+        std::copy(J.plan.lbox.begin(), J.plan.lbox.end(), h_lbox.begin() + 4 * o_blk);
+        JobDev& D = h_jobs[j];
+        D.img = images[J.img].data;
+        D.mask = masks[J.img].data;
+        D.out = outs[J.img].data;
+        D.img_pitch = images[J.img].pitch;
+        D.mask_pitch = masks[J.img].pitch;
+        D.out_pitch = outs[J.img].pitch;
+        D.recon = (double*)ws.recon.p + o_pix;
+        D.status = (uint8_t*)ws.status.p + o_pix;
+        D.W = J.W;
+        D.H = J.H;
+        D.ox = J.ox;
+        D.oy = J.oy;
+        D.cx0 = J.cx0;
+        D.cy0 = J.cy0;
+        D.cx1 = J.cx1;
+        D.cy1 = J.cy1;
+        D.fw = J.plan.fw;
+        D.fh = J.plan.fh;
+        D.owner = (const int32_t*)ws.owner.p + o_cell;
+        D.desc = (const int4*)ws.desc.p + o_blk;
+        D.lbox = (const int4*)ws.lbox.p + o_blk;
+        D.done = (int32_t*)ws.done.p + o_blk;
+        D.n_blocks = (int32_t)nb;
+        const bool tr = p->trace_sel && p->tiling == FSE_WHOLE && n == 1;
+        D.trace = tr ? p->trace_sel : nullptr;
+        D.trace_stride = tr ? p->trace_stride : 0;
+        D.trace_cap = tr ? p->trace_capacity : 0;
+        o_pix += (size_t)J.W * J.H;
+        o_cell += J.plan.owner.size();
+        o_blk += nb;
+    }
+    auto up = [&](DevBuf& b, const void* h, size_t bytes) {
+        return bytes ? hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    if ((e = up(ws.owner, h_owner.data(), n_cells * 4)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.desc, h_desc.data(), n_blk * 16)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.lbox, h_lbox.data(), n_blk * 16)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.tickets, tickets.data(), (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.jobs, h_jobs.data(), jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
+
+    LaunchArgs a{};
+    if ((s = upload_tables(ws, cls, p->rho, st, a)) != FSE_OK) return s;
+    a.jobs = (const JobDev*)ws.jobs.p;
+    a.tickets = (const int2*)ws.tickets.p;
+    a.n_tickets = (int32_t)ntk;
+    int32_t* misc = (int32_t*)ws.misc.p;
+    a.error = misc;
+    a.degenerate = (int64_t*)(misc + 2);
+    a.Bmin = cls.back().B;
+    int reach = 0;
+    for (auto& c : cls) reach = std::max(reach, c.b);
+    a.reach = reach;
+    a.gamma = p->gamma;
+    a.delta = p->recon_weight;
+    a.wait_limit = (int64_t)5 * 100000000;  // 5 s at 100 MHz
+    stats.host_plan_ms = now_ms() - t0;
+
+    int max_w = 1, max_h = 1;
+    for (auto& J : jobs) {
+        max_w = std::max(max_w, J.W);
+        max_h = std::max(max_h, J.H);
+    }
+    int32_t* counter = misc + 1;
+    e = launch_init_job(a.jobs, (int)jobs.size(), max_w, max_h, counter, a.error, a.degenerate, st);
+    if (e != hipSuccess) return from_hip(e);
+    if (ntk > 0) {
+        if (p->schedule == FSE_SCHED_PERSISTENT) {
+            a.counter = counter;
+            int grid = p->workgroups > 0 ? p->workgroups : persistent_grid();
+            grid = (int)std::min<int64_t>(grid, ntk);
+            e = launch_blocks_at(a, grid, 0, st);
+        } else if (p->schedule == FSE_SCHED_WAVEFRONT) {
+            a.counter = nullptr;
+            for (int k = 0; k <= max_key && e == hipSuccess; ++k) {
+                const int cnt = kstart[k + 1] - kstart[k];
+                if (cnt > 0) e = launch_blocks_at(a, cnt, kstart[k], st);
+            }
+        } else {
+            // plain path: one launch per block, raster order of each job
+            a.counter = nullptr;
+            std::vector<int32_t> raster(2 * ntk);
+            size_t q = 0;
+            for (size_t j = 0; j < jobs.size(); ++j)
+                for (size_t b = 0; b < jobs[j].plan.key.size(); ++b) {
+                    raster[2 * q] = (int32_t)j;
+                    raster[2 * q + 1] = (int32_t)b;
+                    ++q;
+                }
+            if ((e = up(ws.tickets, raster.data(), (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
+            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, 1, (int)k, st);
+        }
+        if (e != hipSuccess) return from_hip(e);
+    }
+    ws.last_stream = st;
+    g_last_stats = stats;
+    return FSE_OK;
+}
+
+}  // namespace fse
+
+using namespace fse;
+
+extern "C" {
+
+const char* fse_status_string(fse_status_t s) {
+    switch (s) {
+        case FSE_OK: return "ok";
+        case FSE_ERR_INVALID_ARG: return "invalid argument";
+        case FSE_ERR_UNSUPPORTED: return "unsupported configuration";
+        case FSE_ERR_BUDGET: return "request exceeds the memory budget";
+        case FSE_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case FSE_ERR_DEVICE: return "device error";
+        case FSE_ERR_TIMEOUT: return "timed out";
+        case FSE_ERR_NOT_FOUND: return "unknown ticket";
+        case FSE_ERR_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+fse_status_t fse_params_default(fse_params_t* p) {
+    if (!p) return FSE_ERR_INVALID_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->n_classes = 1;
+    p->classes[0] = {4, 14, 100};
+    p->rho = 0.8;
+    p->gamma = 0.5;
+    p->recon_weight = 0.5;
+    p->precision = FSE_PREC_F64;
+    p->schedule = FSE_SCHED_PERSISTENT;
+    p->tiling = FSE_WHOLE;
+    p->n_tiles = 1;
+    p->overlap = 32;
+    p->align = 16;
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align, fse_tile_t* tiles) {
+    if (W < 1 || H < 1 || N < 1 || d < 0 || align < 1 || !tiles) return FSE_ERR_INVALID_ARG;
+    if ((int64_t)N > (int64_t)W * H) return FSE_ERR_INVALID_ARG;
+    std::vector<int32_t> t;
+    if (!compact_tiling(W, H, N, t)) return FSE_ERR_INVALID_ARG;
+    for (int i = 0; i < N; ++i) {
+        int x = t[4 * i], y = t[4 * i + 1];
+        int x1 = x + t[4 * i + 2], y1 = y + t[4 * i + 3];
+        if (align > 1) {
+            x = x / align * align;
+            y = y / align * align;
+            x1 = (x1 == W) ? W : x1 / align * align;
+            y1 = (y1 == H) ? H : y1 / align * align;
+        }
+        fse_tile_t& T = tiles[i];
+        T.x = x;
+        T.y = y;
+        T.w = x1 - x;
+        T.h = y1 - y;
+        T.ox = std::max(0, x - d);
+        T.oy = std::max(0, y - d);
+        T.ow = std::min(W, x1 + d) - T.ox;
+        T.oh = std::min(H, y1 + d) - T.oy;
+    }
+    return FSE_OK;
+}
+
+fse_status_t fse_extrapolate(const fse_image_t* image, const fse_mask_t* mask, const fse_params_t* p,
+                             fse_image_t* out, void* stream) {
+    if (!image || !mask || !out) return FSE_ERR_INVALID_ARG;
+    return run_batch(1, image, mask, p, out, (hipStream_t)stream);
+}
+
+fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
+                                   const fse_params_t* p, fse_image_t* outs, void* stream) {
+    return run_batch(n, images, masks, p, outs, (hipStream_t)stream);
+}
+
+fse_status_t fse_last_stats(fse_run_stats_t* st) {
+    if (!st) return FSE_ERR_INVALID_ARG;
+    *st = g_last_stats;
+    return FSE_OK;
+}
+
+fse_status_t fse_release(void) {
+    release_all_workspaces();
+    return FSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,456 @@
+// fse_kernels.hip -- gfx950 kernels of Frequency Selective Extrapolation.
+//
+// One processing block per 256-thread workgroup (four wave64).  Per block:
+//   1. wait until every earlier block that shares pixels with this block's
+//      support window (in either direction) has finished, so the window holds
+//      exactly what a strict raster-order pass would see;
+//   2. stage the M x M support window: weights w = rho^dist (known pixels),
+//      delta rho^dist (reconstructed pixels), 0 (lost or outside); W0 = sum w;
+//   3. weighted forward 2-D DFT of w*s and of w as F X F on the FP64 matrix
+//      cores (v_mfma_f64_16x16x4f64), F[k,m] = e^{-2 pi i k m / M};
+//   4. K greedy steps: argmax of |R|^2 (ties to the smallest index),
+//      alpha = gamma R[u,v] / W0, R -= alpha * W shifted by (u,v);
+//   5. evaluate Re sum alpha e^{+2 pi i (u m + v n)/M} at the block's lost
+//      pixels, store them (FP64 working copy and float32 output), publish.
+// The block model is Sec. II of the paper; steps 1 and the persistent
+// ticket dispatch are this library's way of running it on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fse_internal.h"
+#include "fse_runtime.h"
+
+namespace fse {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// working-state initialisation
+// ---------------------------------------------------------------------------
+__global__ void k_init_job(const JobDev* __restrict__ jobs, int32_t* counter, int32_t* error,
+                           int64_t* degenerate) {
+    const JobDev& J = jobs[blockIdx.z];
+    // clear the completion flags of this job's blocks
+    const int64_t flat = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nflat = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+    for (int64_t i = flat; i < J.n_blocks; i += nflat) J.done[i] = 0;
+    if (flat == 0 && blockIdx.z == 0) {
+        if (counter) *counter = 0;
+        *error = 0;
+        *degenerate = 0;
+    }
+    const int y = blockIdx.y;
+    if (y >= J.H) return;
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < J.W; x += gridDim.x * blockDim.x) {
+        const int gy = J.oy + y, gx = J.ox + x;
+        const uint8_t lost = J.mask[(int64_t)gy * J.mask_pitch + gx] != 0;
+        J.status[(int64_t)y * J.W + x] = lost ? kLost : kKnown;
+        if (!lost && y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
+            J.out[(int64_t)gy * J.out_pitch + gx] = J.img[(int64_t)gy * J.img_pitch + gx];
+    }
+}
+
+hipError_t launch_init_job(const JobDev* jobs_dev, int n_jobs, int max_w, int max_h, int32_t* counter,
+                           int32_t* error, int64_t* degenerate, hipStream_t st) {
+    if (n_jobs <= 0) return hipSuccess;
+    dim3 grid((max_w + 255) / 256, max_h, n_jobs);
+    hipLaunchKernelGGL(k_init_job, grid, dim3(256), 0, st, jobs_dev, counter, error, degenerate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ld_acquire(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// (e, idx) pair ordering: larger energy first, smaller index on equal energy
+__device__ __forceinline__ bool better(double e1, int i1, double e0, int i0) {
+    return e1 > e0 || (e1 == e0 && i1 < i0);
+}
+
+__device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, int by0, int bx0, int by1,
+                                           int bx1) {
+    return ay0 < by1 && by0 < ay1 && ax0 < bx1 && bx0 < ax1;
+}
+
+// LDS layout (doubles) for M = 32
+constexpr int kLd = 33;                 // padded row stride of the DFT operands
+constexpr int kBufDoubles = 6144;       // 48 KB staging / spectra area
+constexpr int kMaxK = 256;
+
+struct Shared32 {
+    double buf[kBufDoubles];
+    double twc[32], tws[32];
+    double part[4];
+    double se[2][4], sr[2][4], si[2][4];
+    int sidx[2][4];
+    int cidx[kMaxK];
+    double car[kMaxK], cai[kMaxK];
+    int job, blk, wait_fail;
+    double W0;
+};
+
+// ---------------------------------------------------------------------------
+// one M = 32 block, FP64 end to end
+// ---------------------------------------------------------------------------
+__device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wv = t >> 6;
+    const int4 d = J.desc[blk];
+    const ClassDev& C = a.cls[d.z];
+    const int B = C.B, b = C.b, K = C.K;
+    constexpr int M = 32;
+    const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
+
+    // ---- stage the window: weights and weighted values --------------------
+    double* Xs = S.buf;            // w * s, [m][n] stride kLd
+    double* Xw = S.buf + M * kLd;  // w
+    double wsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int m = (t >> 5) + 8 * j, n = t & 31;
+        const int y = wy + m, x = wx + n;
+        double w = 0.0, v = 0.0;
+        if (y >= 0 && y < J.H && x >= 0 && x < J.W) {
+            const int64_t q = (int64_t)y * J.W + x;
+            const uint8_t st = J.status[q];
+            if (st == kKnown) {
+                w = C.wtab[m * M + n];
+                v = (double)J.img[(int64_t)(J.oy + y) * J.img_pitch + (J.ox + x)];
+            } else if (st == kRecon) {
+                w = a.delta * C.wtab[m * M + n];
+                v = J.recon[q];
+            }
+        }
+        Xs[m * kLd + n] = w * v;
+        Xw[m * kLd + n] = w;
+        wsum += w;
+    }
+    for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
+    if (lane == 0) S.part[wv] = wsum;
+    __syncthreads();
+    const double W0 = ((S.part[0] + S.part[1]) + S.part[2]) + S.part[3];
+
+    // ---- stage 1: T = F X on the FP64 matrix cores --------------------------
+    // wave 0: cos * (w s), wave 1: -sin * (w s), wave 2: cos * w, wave 3: -sin * w
+    const int li = lane & 15, lk = lane >> 4;
+    dbl4 acc[4];
+    {
+        const double* X = (wv >> 1) ? Xw : Xs;
+        const bool sn = wv & 1;
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+            const int ti = tile >> 1, tj = tile & 1;
+            dbl4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int row = ti * 16 + li, col = kk * 4 + lk;
+                const int p = (row * col) & 31;
+                const double av = sn ? -S.tws[p] : S.twc[p];
+                const double bv = X[(kk * 4 + lk) * kLd + tj * 16 + li];
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+            }
+            acc[tile] = c;
+        }
+    }
+    __syncthreads();  // every wave done reading X
+    {
+        double* T = S.buf + wv * (M * kLd);
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+            const int ti = tile >> 1, tj = tile & 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[(ti * 16 + lk + 4 * r) * kLd + tj * 16 + li] = acc[tile][r];
+        }
+    }
+    __syncthreads();
+
+    // ---- stage 2: R = T F --------------------------------------------------
+    // R_re = T0 C + T1 sin, R_im = T1 C - T0 sin (same for the weights with T2, T3)
+    {
+        const double* A1 = S.buf + ((wv >> 1) * 2) * (M * kLd);
+        const double* A2 = A1 + M * kLd;
+        const bool odd = wv & 1;
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+            const int ti = tile >> 1, tj = tile & 1;
+            dbl4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int row = kk * 4 + lk, col = tj * 16 + li;
+                const int p = (row * col) & 31;
+                const double a1 = A1[(ti * 16 + li) * kLd + kk * 4 + lk];
+                const double a2 = A2[(ti * 16 + li) * kLd + kk * 4 + lk];
+                const double b1 = odd ? -S.tws[p] : S.twc[p];
+                const double b2 = odd ? S.twc[p] : S.tws[p];
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, c, 0, 0, 0);
+            }
+            acc[tile] = c;
+        }
+    }
+    __syncthreads();  // T no longer read
+    double* Wd = S.buf;         // weight spectrum, rows duplicated: [64][32] complex
+    double* Rl = S.buf + 4096;  // residual spectrum [32][32] complex
+    {
+        const int part = wv & 1;  // 0 = real, 1 = imaginary
+#pragma unroll
+        for (int tile = 0; tile < 4; ++tile) {
+            const int ti = tile >> 1, tj = tile & 1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = ti * 16 + lk + 4 * r, l = tj * 16 + li;
+                const double v = acc[tile][r];
+                if (wv < 2) {
+                    Rl[(k * 32 + l) * 2 + part] = v;
+                } else {
+                    Wd[(k * 32 + l) * 2 + part] = v;
+                    Wd[((k + 32) * 32 + l) * 2 + part] = v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- K greedy steps ----------------------------------------------------
+    const int k0 = t >> 5, l = t & 31;
+    double rr[4], ri[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        rr[j] = Rl[((k0 + 8 * j) * 32 + l) * 2];
+        ri[j] = Rl[((k0 + 8 * j) * 32 + l) * 2 + 1];
+    }
+    const bool live = W0 > 0.0;
+    int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
+    for (int it = 0; it < K && live; ++it) {
+        // local maximiser (elements are visited in increasing index order)
+        double be = rr[0] * rr[0] + ri[0] * ri[0];
+        int bj = 0;
+#pragma unroll
+        for (int j = 1; j < 4; ++j) {
+            const double e = rr[j] * rr[j] + ri[j] * ri[j];
+            if (e > be) {
+                be = e;
+                bj = j;
+            }
+        }
+        int bidx = (k0 + 8 * bj) * 32 + l;
+        double we = be;
+        int widx = bidx;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double oe = __shfl_xor(we, off);
+            const int oi = __shfl_xor(widx, off);
+            if (better(oe, oi, we, widx)) {
+                we = oe;
+                widx = oi;
+            }
+        }
+        const int p = it & 1;
+        if (bidx == widx) {  // the lane that owns the wave's maximiser publishes it
+            double vr = rr[0], vi = ri[0];
+#pragma unroll
+            for (int j = 1; j < 4; ++j)
+                if (bj == j) {
+                    vr = rr[j];
+                    vi = ri[j];
+                }
+            S.se[p][wv] = we;
+            S.sidx[p][wv] = widx;
+            S.sr[p][wv] = vr;
+            S.si[p][wv] = vi;
+        }
+        __syncthreads();
+        double E = S.se[p][0];
+        int IDX = S.sidx[p][0];
+        double Rr = S.sr[p][0], Ri = S.si[p][0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+            const double e = S.se[p][q];
+            const int i = S.sidx[p][q];
+            if (better(e, i, E, IDX)) {
+                E = e;
+                IDX = i;
+                Rr = S.sr[p][q];
+                Ri = S.si[p][q];
+            }
+        }
+        const double ar = a.gamma * Rr / W0;
+        const double ai = a.gamma * Ri / W0;
+        if (t == 0) {
+            S.cidx[it] = IDX;
+            S.car[it] = ar;
+            S.cai[it] = ai;
+            if (trace) trace[it] = IDX;
+        }
+        const int u = IDX >> 5, v = IDX & 31;
+        const double* wrow = Wd + (((k0 - u + 32) * 32 + ((l - v) & 31)) * 2);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double wr = wrow[j * 8 * 32 * 2];
+            const double wi = wrow[j * 8 * 32 * 2 + 1];
+            rr[j] -= ar * wr - ai * wi;
+            ri[j] -= ar * wi + ai * wr;
+        }
+    }
+    if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
+    __syncthreads();
+
+    // ---- synthesis at the block's lost pixels ------------------------------
+    // B*B pixels, (256 / B^2) threads per pixel, each summing every g-th step
+    const int npx = B * B;
+    const int g = kThreads / npx;  // 16 (B=4), 4 (B=8), 1 (B=16)
+    const int px = t / g, sub = t % g;
+    const int py = px / B, pxx = px % B;
+    const int m = b + py, n = b + pxx;
+    double val = 0.0;
+    if (live) {
+        for (int it = sub; it < K; it += g) {
+            const int idx = S.cidx[it];
+            const int u = idx >> 5, v = idx & 31;
+            const int ph = (u * m + v * n) & 31;
+            val += S.car[it] * S.twc[ph] - S.cai[it] * S.tws[ph];
+        }
+    }
+    for (int off = g >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
+    if (sub == 0) {
+        const int y = d.x + py, x = d.y + pxx;
+        if (y < J.H && x < J.W) {
+            const int64_t q = (int64_t)y * J.W + x;
+            if (J.status[q] == kLost) {
+                J.recon[q] = val;
+                J.status[q] = kRecon;
+                if (y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
+                    J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
+            }
+        }
+    }
+    // make this wave's pixel stores visible device-wide before the block is
+    // published (the completion flag is set by one thread after a barrier)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
+// ---------------------------------------------------------------------------
+// dependency wait: every earlier block whose lost pixels meet this block's
+// window, or whose window meets this block's lost pixels
+// ---------------------------------------------------------------------------
+__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
+    const int4 d = J.desc[blk];
+    const int4 lb = J.lbox[blk];
+    const ClassDev& Cj = a.cls[d.z];
+    const int Bm = a.Bmin;
+    // fine cells that may hold an interacting block
+    const int ry0 = d.x - a.reach, rx0 = d.y - a.reach;
+    const int ry1 = d.x + Cj.B + a.reach, rx1 = d.y + Cj.B + a.reach;
+    const int fy0 = max(0, ry0 >= 0 ? ry0 / Bm : 0), fx0 = max(0, rx0 >= 0 ? rx0 / Bm : 0);
+    const int fy1 = min(J.fh - 1, (ry1 - 1) / Bm), fx1 = min(J.fw - 1, (rx1 - 1) / Bm);
+    const int nw = fx1 - fx0 + 1;
+    const int ncell = (fy1 - fy0 + 1) * nw;
+    // window of j
+    const int jwy0 = d.x - Cj.b, jwx0 = d.y - Cj.b;
+    const int jwy1 = d.x + Cj.B + Cj.b, jwx1 = d.y + Cj.B + Cj.b;
+    for (int c = threadIdx.x; c < ncell; c += kThreads) {
+        const int fy = fy0 + c / nw, fx = fx0 + c % nw;
+        const int i = J.owner[fy * J.fw + fx];
+        if (i < 0 || i >= blk) continue;
+        const int4 di = J.desc[i];
+        // count each neighbour once: at its first cell inside the scanned range
+        const int iy = max(fy0, di.x / Bm), ix = max(fx0, di.y / Bm);
+        if (iy != fy || ix != fx) continue;
+        const int4 li = J.lbox[i];
+        const ClassDev& Ci = a.cls[di.z];
+        const bool e1 = boxes_meet(li.x, li.y, li.z, li.w, jwy0, jwx0, jwy1, jwx1);
+        const bool e2 = boxes_meet(lb.x, lb.y, lb.z, lb.w, di.x - Ci.b, di.y - Ci.b, di.x + Ci.B + Ci.b,
+                                   di.y + Ci.B + Ci.b);
+        if (!(e1 || e2)) continue;
+        if (ld_acquire(&J.done[i]) == 0) {
+            const uint64_t t0 = wall_clock64();
+            while (ld_acquire(&J.done[i]) == 0) {
+                __builtin_amdgcn_s_sleep(2);
+                if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
+                    S.wait_fail = 1;
+                    atomicOr(a.error, 1);
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// ---------------------------------------------------------------------------
+// block kernel: tickets in dispatch order; with counter != null the grid is
+// persistent and workgroups draw tickets until none is left
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_fse_blocks(LaunchArgs a, int ticket_base) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Shared32& S = *reinterpret_cast<Shared32*>(smem_raw);
+    const int t = threadIdx.x;
+    if (t < 32) {
+        S.twc[t] = a.tw32[t];
+        S.tws[t] = a.tw32[32 + t];
+    }
+    for (;;) {
+        if (t == 0) {
+            int tk;
+            if (a.counter)
+                tk = __hip_atomic_fetch_add(a.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                tk = ticket_base + blockIdx.x;
+            if (tk < a.n_tickets) {
+                const int2 tkt = a.tickets[tk];
+                S.job = tkt.x;
+                S.blk = tkt.y;
+            } else {
+                S.job = -1;
+                S.blk = -1;
+            }
+            S.wait_fail = 0;
+        }
+        __syncthreads();
+        const int job = S.job, blk = S.blk;
+        if (job < 0) break;
+        const JobDev& J = a.jobs[job];
+        wait_predecessors(a, J, blk, S);
+        process_block32(a, J, blk, S);
+        __syncthreads();
+        if (t == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(&J.done[blk], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!a.counter) break;
+        __syncthreads();
+    }
+}
+
+size_t shared_bytes_blocks() { return sizeof(Shared32); }
+
+int persistent_grid() {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipFuncSetAttribute((const void*)k_fse_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)sizeof(Shared32));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fse_blocks, kThreads, sizeof(Shared32)) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return std::max(1, cus) * per_cu;
+}
+
+hipError_t launch_blocks_at(const LaunchArgs& a, int grid, int ticket_base, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute((const void*)k_fse_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(Shared32));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_fse_blocks, dim3(grid), dim3(kThreads), sizeof(Shared32), st, a, ticket_base);
+    return hipGetLastError();
+}
+
+}  // namespace fse

@@ -1,0 +1,46 @@
+// fse_plan.h -- host planning of processing blocks, dependency keys and
+// tiles (internal to libfse).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+namespace fse {
+
+struct ClassCfg {
+    int B, b, K, M;
+};
+
+// Processing blocks of one region (a whole image or one extended tile).
+struct RegionPlan {
+    int W = 0, H = 0;    // region size
+    int fw = 0, fh = 0;  // fine-cell grid (cells of the smallest block edge)
+    std::vector<int32_t> owner;  // fw*fh: owning block of the cell's lost pixels, -1 none
+    std::vector<int32_t> desc;   // 4 per block: y0, x0, class, 0 (raster order)
+    std::vector<int32_t> lbox;   // 4 per block: lost-pixel bounding box y0, x0, y1, x1 (exclusive)
+    std::vector<int32_t> key;    // wavefront key per block (a topological order of the dependencies)
+    int64_t lost_pixels = 0;
+};
+
+// Block geometry shared by the planner and the kernels: the largest class
+// whose aligned square is entirely lost (and inside the region) takes it;
+// the smallest class takes every remaining cell holding a lost pixel.
+// mask: region view (row pitch in elements).  Returns false on bad classes.
+bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::vector<ClassCfg>& cls,
+                 RegionPlan& out);
+
+// Key slope: a block can only interact with blocks whose corner lies at most
+// D fine cells to its right in an earlier row, so key = cx + (D + 1) cy
+// increases along every dependency.
+int key_reach_cells(const std::vector<ClassCfg>& cls);
+
+// Raster-order dependency test of two blocks (i before j): i's lost pixels
+// meet j's window, or j's lost pixels meet i's window.
+bool blocks_interact(const int32_t* desc_i, const int32_t* lbox_i, const int32_t* desc_j,
+                     const int32_t* lbox_j, const std::vector<ClassCfg>& cls);
+
+// Algorithm 1 of the paper (eqs. (1)-(5)): core tiles x, y, w, h.
+bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh);
+
+}  // namespace fse

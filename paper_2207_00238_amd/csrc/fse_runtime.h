@@ -1,0 +1,37 @@
+// fse_runtime.h -- host runtime pieces of libfse: device buffers and the
+// per-stream workspace (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/fse.h"
+
+namespace fse {
+
+// A grow-only device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n);
+    void release();
+};
+
+// Everything one extrapolation call needs on the device.  Calls that use the
+// same stream share one workspace and are serialised by its mutex.
+struct Workspace {
+    std::mutex mu;
+    DevBuf recon, status, owner, desc, lbox, done, tickets, jobs, misc, tabs;
+    std::vector<double> tab_key;  // parameters the uploaded tables were built for
+    hipStream_t last_stream = nullptr;
+    void free_all();
+};
+
+fse_status_t from_hip(hipError_t e);
+Workspace* workspace_for(hipStream_t st);
+void release_all_workspaces();
+int persistent_grid();  // resident workgroups of the block kernel on the current device
+
+}  // namespace fse

@@ -1,0 +1,85 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+validates arguments on the host, and its tiling equals the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_00238_amd import fse
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "fse.h")).read()
+    return sorted(set(re.findall(r"\b(fse_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    L = fse.lib()
+    names = _declared()
+    assert set(names) == set(fse.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("W,H,N,d,align", [(1024, 480, 22, 0, 1), (1920, 1080, 32, 32, 1), (3840, 2160, 64, 32, 16),
+                                           (480, 1920, 7, 8, 4), (1000, 999, 13, 3, 1), (128, 128, 1, 32, 16)])
+def test_plan_tiles_matches_oracle(W, H, N, d, align):
+    got = fse.fse_plan_tiles(W, H, N, d, align)
+    ref = O.tiles_with_stripe(W, H, N, d, align)
+    assert [(tuple(c), tuple(e)) for c, e in got] == [(tuple(c), tuple(e)) for c, e in ref]
+
+
+def test_plan_tiles_rejects_bad_arguments():
+    L = fse.lib()
+    tiles = (fse.fse_tile_t * 4)()
+    assert L.fse_plan_tiles(0, 10, 4, 0, 1, tiles) == fse.FSE_ERR_INVALID_ARG
+    assert L.fse_plan_tiles(10, 10, 0, 0, 1, tiles) == fse.FSE_ERR_INVALID_ARG
+    assert L.fse_plan_tiles(10, 10, 4, -1, 1, tiles) == fse.FSE_ERR_INVALID_ARG
+    assert L.fse_plan_tiles(2, 1, 4, 0, 1, tiles) == fse.FSE_ERR_INVALID_ARG
+
+
+def _call(p, W=64, H=64):
+    L = fse.lib()
+    im = fse.fse_image_t(0x1000, W, H, W)
+    mk = fse.fse_mask_t(0x2000, W, H, W)
+    ot = fse.fse_image_t(0x3000, W, H, W)
+    return L.fse_extrapolate(ctypes.byref(im), ctypes.byref(mk), ctypes.byref(p), ctypes.byref(ot), None)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("rho", 0.0, fse.FSE_ERR_INVALID_ARG), ("rho", 1.5, fse.FSE_ERR_INVALID_ARG),
+    ("gamma", 2.0, fse.FSE_ERR_INVALID_ARG), ("gamma", 0.0, fse.FSE_ERR_INVALID_ARG),
+    ("recon_weight", 0.0, fse.FSE_ERR_INVALID_ARG), ("schedule", 9, fse.FSE_ERR_INVALID_ARG),
+    ("tiling", 5, fse.FSE_ERR_INVALID_ARG), ("n_classes", 0, fse.FSE_ERR_INVALID_ARG),
+])
+def test_parameter_validation(field, value, code):
+    p = fse.fse_params_default()
+    setattr(p, field, value)
+    assert _call(p) == code
+
+
+def test_unsupported_window_and_bad_images():
+    p = fse.fse_params_default(classes=((4, 10, 100),))  # M = 24
+    assert _call(p) == fse.FSE_ERR_UNSUPPORTED
+    p = fse.fse_params_default()
+    L = fse.lib()
+    im = fse.fse_image_t(0x1000, 64, 64, 64)
+    mk = fse.fse_mask_t(0x2000, 64, 32, 64)  # size mismatch
+    ot = fse.fse_image_t(0x3000, 64, 64, 64)
+    assert L.fse_extrapolate(ctypes.byref(im), ctypes.byref(mk), ctypes.byref(p), ctypes.byref(ot),
+                             None) == fse.FSE_ERR_INVALID_ARG
+    ot2 = fse.fse_image_t(0x1000, 64, 64, 64)  # aliasing the input
+    mk2 = fse.fse_mask_t(0x2000, 64, 64, 64)
+    assert L.fse_extrapolate(ctypes.byref(im), ctypes.byref(mk2), ctypes.byref(p), ctypes.byref(ot2),
+                             None) == fse.FSE_ERR_INVALID_ARG
+
+
+def test_status_strings():
+    L = fse.lib()
+    for code in range(-8, 1):
+        assert L.fse_status_string(code)

@@ -97,7 +97,8 @@ typedef struct {
  * Parameters.  classes[0..n_classes-1] are ordered by decreasing block edge,
  * each edge a multiple of the next; every class but the last takes aligned
  * squares that are entirely lost, the last class takes the aligned cells
- * that still hold a lost pixel.  Supported windows: M = 32 and M = 64.
+ * that still hold a lost pixel.  Block edges are powers of two up to 16;
+ * supported windows: M = 32.
  * rho in (0,1]: isotropic weight decay rho^distance; recon_weight in (0,1]:
  * extra factor for pixels reconstructed by earlier blocks; gamma in (0,2):
  * orthogonality-deficiency compensation.
@@ -114,6 +115,7 @@ typedef struct {
     int32_t tiling;    /* FSE_WHOLE or FSE_TILED */
     int32_t n_tiles, overlap, align; /* FSE_TILED: tiles N, stripe d, grid alignment */
     int32_t workgroups;              /* persistent grid size; 0 = automatic */
+    int32_t block_waves;             /* wave64s per processing block: 1, 2 or 4; 0 = automatic */
     int32_t* trace_sel;
     int32_t trace_stride;
     int64_t trace_capacity;
@@ -127,6 +129,8 @@ typedef struct {
     int64_t n_jobs;       /* images x tiles */
     int32_t wavefront_keys;
     double host_plan_ms;  /* host-side planning time */
+    double kernel_ms;     /* device time of the block kernel(s), HIP events on the call's stream */
+    int32_t device_error; /* non-zero: a dependency wait hit its time limit (results invalid) */
 } fse_run_stats_t;
 
 const char* fse_status_string(fse_status_t s);
@@ -161,7 +165,8 @@ fse_status_t fse_extrapolate(const fse_image_t* image, const fse_mask_t* mask, c
 fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
                                    const fse_params_t* p, fse_image_t* outs, void* stream);
 
-/* Statistics of the last extrapolate call made by this thread. */
+/* Statistics of the last extrapolate call made by this thread; waits for
+ * that call's stream to finish its work. */
 fse_status_t fse_last_stats(fse_run_stats_t* st);
 
 /* Free all cached device workspace (waits for the streams that use it). */

@@ -19,6 +19,7 @@
 namespace fse {
 
 thread_local fse_run_stats_t g_last_stats{};
+thread_local Workspace* g_last_ws = nullptr;
 
 static double now_ms() {
     using namespace std::chrono;
@@ -73,6 +74,7 @@ Workspace* workspace_for(hipStream_t st) {
 
 void release_all_workspaces() {
     std::lock_guard<std::mutex> lk(g_ws_mu);
+    g_last_ws = nullptr;
     for (auto& kv : g_ws) {
         std::lock_guard<std::mutex> wl(kv.second->mu);
         hipStreamSynchronize(kv.first.second);
@@ -84,6 +86,13 @@ void release_all_workspaces() {
 void Workspace::free_all() {
     for (DevBuf* b : {&recon, &status, &owner, &desc, &lbox, &done, &tickets, &jobs, &misc, &tabs}) b->release();
     tab_key.clear();
+    if (host_mask) hipHostFree(host_mask);
+    host_mask = nullptr;
+    host_mask_cap = 0;
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    ev0 = ev1 = nullptr;
+    timed = false;
 }
 
 // ---------------------------------------------------------------------------
@@ -104,7 +113,7 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
         if (k.block < 1 || k.border < 0 || k.iters < 0 || k.iters > 256) return FSE_ERR_INVALID_ARG;
         const int M = k.block + 2 * k.border;
         if (M != 32) return FSE_ERR_UNSUPPORTED;
-        if (k.block * k.block > kThreads || (kThreads % (k.block * k.block)) != 0) return FSE_ERR_UNSUPPORTED;
+        if (k.block > 16 || (k.block & (k.block - 1)) != 0) return FSE_ERR_UNSUPPORTED;
         cls.push_back({k.block, k.border, k.iters, M});
     }
     for (int c = 0; c + 1 < p->n_classes; ++c)
@@ -114,6 +123,8 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
         if (p->align % cls.back().B != 0 || p->overlap % p->align != 0) return FSE_ERR_INVALID_ARG;
         if (p->align % cls.front().B != 0) return FSE_ERR_INVALID_ARG;
     }
+    if (p->block_waves != 0 && p->block_waves != 1 && p->block_waves != 2 && p->block_waves != 4)
+        return FSE_ERR_INVALID_ARG;
     if (p->trace_sel) {
         int kmax = 0;
         for (auto& c : cls) kmax = std::max(kmax, c.K);
@@ -210,11 +221,20 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     const double t0 = now_ms();
     // ---- masks to the host, regions, plans ---------------------------------
     std::vector<HostJob> jobs;
-    std::vector<std::vector<uint8_t>> hmask(n);
+    std::vector<size_t> moff(n + 1, 0);
+    for (int i = 0; i < n; ++i) moff[i + 1] = moff[i] + (size_t)images[i].width * images[i].height;
+    if (ws.host_mask_cap < moff[n]) {
+        if (ws.host_mask) hipHostFree(ws.host_mask);
+        ws.host_mask = nullptr;
+        ws.host_mask_cap = 0;
+        if ((e = hipHostMalloc((void**)&ws.host_mask, moff[n], hipHostMallocDefault)) != hipSuccess)
+            return from_hip(e);
+        ws.host_mask_cap = moff[n];
+    }
     for (int i = 0; i < n; ++i) {
         const int W = images[i].width, H = images[i].height;
-        hmask[i].resize((size_t)W * H);
-        e = hipMemcpy2DAsync(hmask[i].data(), W, masks[i].data, masks[i].pitch, W, H, hipMemcpyDeviceToHost, st);
+        e = hipMemcpy2DAsync(ws.host_mask + moff[i], W, masks[i].data, masks[i].pitch, W, H, hipMemcpyDeviceToHost,
+                             st);
         if (e != hipSuccess) return from_hip(e);
     }
     e = hipStreamSynchronize(st);
@@ -236,12 +256,11 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
         }
     }
     for (auto& J : jobs) {
-        const uint8_t* mk = hmask[J.img].data() + (size_t)J.oy * images[J.img].width + J.ox;
+        const uint8_t* mk = ws.host_mask + moff[J.img] + (size_t)J.oy * images[J.img].width + J.ox;
         if (!plan_region(mk, images[J.img].width, J.W, J.H, cls, J.plan)) return FSE_ERR_INVALID_ARG;
         stats.n_blocks += (int64_t)(J.plan.desc.size() / 4);
     }
-    for (int i = 0; i < n; ++i)
-        for (uint8_t v : hmask[i]) stats.n_lost_pixels += v != 0;
+    for (auto& J : jobs) stats.n_lost_pixels += J.plan.lost_pixels;
     stats.n_jobs = (int64_t)jobs.size();
 
     // ---- tickets: all blocks of all jobs ordered by wavefront key -----------
@@ -359,17 +378,23 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     int32_t* counter = misc + 1;
     e = launch_init_job(a.jobs, (int)jobs.size(), max_w, max_h, counter, a.error, a.degenerate, st);
     if (e != hipSuccess) return from_hip(e);
+    if (!ws.ev0) {
+        if ((e = hipEventCreate(&ws.ev0)) != hipSuccess) return from_hip(e);
+        if ((e = hipEventCreate(&ws.ev1)) != hipSuccess) return from_hip(e);
+    }
+    if ((e = hipEventRecord(ws.ev0, st)) != hipSuccess) return from_hip(e);
+    const int nw = p->block_waves > 0 ? p->block_waves : 4;
     if (ntk > 0) {
         if (p->schedule == FSE_SCHED_PERSISTENT) {
             a.counter = counter;
-            int grid = p->workgroups > 0 ? p->workgroups : persistent_grid();
+            int grid = p->workgroups > 0 ? p->workgroups : persistent_grid(nw);
             grid = (int)std::min<int64_t>(grid, ntk);
-            e = launch_blocks_at(a, grid, 0, st);
+            e = launch_blocks_at(a, nw, grid, 0, st);
         } else if (p->schedule == FSE_SCHED_WAVEFRONT) {
             a.counter = nullptr;
             for (int k = 0; k <= max_key && e == hipSuccess; ++k) {
                 const int cnt = kstart[k + 1] - kstart[k];
-                if (cnt > 0) e = launch_blocks_at(a, cnt, kstart[k], st);
+                if (cnt > 0) e = launch_blocks_at(a, nw, cnt, kstart[k], st);
             }
         } else {
             // plain path: one launch per block, raster order of each job
@@ -383,12 +408,15 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
                     ++q;
                 }
             if ((e = up(ws.tickets, raster.data(), (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
-            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, 1, (int)k, st);
+            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, 1, (int)k, st);
         }
         if (e != hipSuccess) return from_hip(e);
     }
+    if ((e = hipEventRecord(ws.ev1, st)) != hipSuccess) return from_hip(e);
+    ws.timed = true;
     ws.last_stream = st;
     g_last_stats = stats;
+    g_last_ws = &ws;
     return FSE_OK;
 }
 
@@ -470,6 +498,23 @@ fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const f
 
 fse_status_t fse_last_stats(fse_run_stats_t* st) {
     if (!st) return FSE_ERR_INVALID_ARG;
+    Workspace* ws = g_last_ws;
+    if (ws) {
+        std::lock_guard<std::mutex> lk(ws->mu);
+        hipError_t e = hipStreamSynchronize(ws->last_stream);
+        if (e != hipSuccess) return from_hip(e);
+        if (ws->timed) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ws->ev0, ws->ev1) == hipSuccess) g_last_stats.kernel_ms = ms;
+        }
+        int32_t misc[4] = {0, 0, 0, 0};
+        if (ws->misc.p && hipMemcpy(misc, ws->misc.p, sizeof(misc), hipMemcpyDeviceToHost) == hipSuccess) {
+            g_last_stats.device_error = misc[0];
+            int64_t deg = 0;
+            std::memcpy(&deg, misc + 2, sizeof(deg));
+            g_last_stats.n_degenerate = deg;
+        }
+    }
     *st = g_last_stats;
     return FSE_OK;
 }

@@ -76,43 +76,88 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
     return ay0 < by1 && by0 < ay1 && ax0 < bx1 && bx0 < ax1;
 }
 
-// LDS layout (doubles) for M = 32
-constexpr int kLd = 33;                 // padded row stride of the DFT operands
-constexpr int kBufDoubles = 6144;       // 48 KB staging / spectra area
+// LDS layout (doubles) for M = 32: the DFT operands X (2 x 32 x 33) and the
+// stage-1 products T (4 x 32 x 33) side by side; afterwards the duplicated
+// weight spectrum (64 x 32 complex) and the residual spectrum (32 x 32
+// complex) reuse the same area.
+constexpr int kLd = 33;  // padded row stride of the DFT operands
+constexpr int kXOff = 0, kTOff = 2 * 32 * kLd;
+constexpr int kBufDoubles = kTOff + 4 * 32 * kLd;  // 6336 doubles
 constexpr int kMaxK = 256;
 
 struct Shared32 {
     double buf[kBufDoubles];
     double twc[32], tws[32];
     double part[4];
-    double se[2][4], sr[2][4], si[2][4];
-    int sidx[2][4];
+    double4 sl[2][4];  // per wave: energy, Re R, Im R, index
     int cidx[kMaxK];
     double car[kMaxK], cai[kMaxK];
     int job, blk, wait_fail;
-    double W0;
 };
 
+// FP64 maximum over a wave64 with DPP moves of the two 32-bit halves;
+// the result is valid in lane 63.
+// Unsigned 32-bit maximum over a wave64 with DPP; the result is valid in
+// lane 63.  Non-negative doubles order like their bit patterns, so the high
+// words of the energies order them up to ties in the high word.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ unsigned dpp_umax_step(unsigned v) {
+    // lanes without a source (and rows outside ROW_MASK) read 0, the identity
+    const unsigned o = (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+    return __builtin_elementwise_max(v, o);
+}
+
+__device__ __forceinline__ unsigned wave_umax(unsigned v) {
+    v = dpp_umax_step<0xB1, 0xF, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_umax_step<0x4E, 0xF, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_umax_step<0x141, 0xF, 0xF>(v);  // row_half_mirror
+    v = dpp_umax_step<0x140, 0xF, 0xF>(v);  // row_mirror
+    v = dpp_umax_step<0x142, 0xA, 0xF>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_umax_step<0x143, 0xC, 0xF>(v);  // row_bcast:31 into rows 2, 3
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Exact maximum of a non-negative double over the wave (uniform result).
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+    const unsigned hi = (unsigned)__double2hiint(v);
+    const unsigned mhi = wave_umax(hi);
+    const bool cand = hi == mhi;
+    unsigned mlo = (unsigned)__double2loint(v);
+    if (__popcll(__ballot(cand)) > 1) {
+        mlo = wave_umax(cand ? (unsigned)__double2loint(v) : 0u);
+    } else {
+        const int l = __ffsll((unsigned long long)__ballot(cand)) - 1;
+        mlo = (unsigned)__builtin_amdgcn_readlane((int)mlo, l);
+    }
+    return __hiloint2double((int)mhi, (int)mlo);
+}
+
+
 // ---------------------------------------------------------------------------
-// one M = 32 block, FP64 end to end
+// one M = 32 block, FP64 end to end, NW wave64 per block
 // ---------------------------------------------------------------------------
+template <int NW>
 __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
+    constexpr int NT = 64 * NW;     // threads
+    constexpr int EPT = 1024 / NT;  // spectrum elements (and window pixels) per thread
+    constexpr int RS = NT / 32;     // row step between a thread's elements
+    constexpr int NMAT = 4 / NW;    // DFT output matrices per wave
+    constexpr int M = 32;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = t >> 6;
     const int4 d = J.desc[blk];
     const ClassDev& C = a.cls[d.z];
     const int B = C.B, b = C.b, K = C.K;
-    constexpr int M = 32;
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
 
     // ---- stage the window: weights and weighted values --------------------
-    double* Xs = S.buf;            // w * s, [m][n] stride kLd
-    double* Xw = S.buf + M * kLd;  // w
+    double* Xs = S.buf + kXOff;    // w * s, [m][n] stride kLd
+    double* Xw = Xs + M * kLd;     // w
     double wsum = 0.0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int m = (t >> 5) + 8 * j, n = t & 31;
+    for (int j = 0; j < EPT; ++j) {
+        const int m = (t >> 5) + RS * j, n = t & 31;
         const int y = wy + m, x = wx + n;
         double w = 0.0, v = 0.0;
         if (y >= 0 && y < J.H && x >= 0 && x < J.W) {
@@ -133,15 +178,19 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
     if (lane == 0) S.part[wv] = wsum;
     __syncthreads();
-    const double W0 = ((S.part[0] + S.part[1]) + S.part[2]) + S.part[3];
+    double W0 = S.part[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) W0 += S.part[q];
 
     // ---- stage 1: T = F X on the FP64 matrix cores --------------------------
-    // wave 0: cos * (w s), wave 1: -sin * (w s), wave 2: cos * w, wave 3: -sin * w
+    // matrix 0: cos * (w s), 1: -sin * (w s), 2: cos * w, 3: -sin * w
     const int li = lane & 15, lk = lane >> 4;
-    dbl4 acc[4];
-    {
-        const double* X = (wv >> 1) ? Xw : Xs;
-        const bool sn = wv & 1;
+    dbl4 acc[NMAT][4];
+#pragma unroll
+    for (int mi = 0; mi < NMAT; ++mi) {
+        const int mat = wv + NW * mi;
+        const double* X = (mat >> 1) ? Xw : Xs;
+        const bool sn = mat & 1;
 #pragma unroll
         for (int tile = 0; tile < 4; ++tile) {
             const int ti = tile >> 1, tj = tile & 1;
@@ -154,27 +203,30 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 const double bv = X[(kk * 4 + lk) * kLd + tj * 16 + li];
                 c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
             }
-            acc[tile] = c;
+            acc[mi][tile] = c;
         }
     }
-    __syncthreads();  // every wave done reading X
-    {
-        double* T = S.buf + wv * (M * kLd);
+#pragma unroll
+    for (int mi = 0; mi < NMAT; ++mi) {
+        double* T = S.buf + kTOff + (wv + NW * mi) * (M * kLd);
 #pragma unroll
         for (int tile = 0; tile < 4; ++tile) {
             const int ti = tile >> 1, tj = tile & 1;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) T[(ti * 16 + lk + 4 * r) * kLd + tj * 16 + li] = acc[tile][r];
+            for (int r = 0; r < 4; ++r) T[(ti * 16 + lk + 4 * r) * kLd + tj * 16 + li] = acc[mi][tile][r];
         }
     }
     __syncthreads();
 
     // ---- stage 2: R = T F --------------------------------------------------
-    // R_re = T0 C + T1 sin, R_im = T1 C - T0 sin (same for the weights with T2, T3)
-    {
-        const double* A1 = S.buf + ((wv >> 1) * 2) * (M * kLd);
+    // output 0: R_re = T0 C + T1 sin, 1: R_im = T1 C - T0 sin, 2 and 3: the
+    // same for the weights with T2, T3
+#pragma unroll
+    for (int mi = 0; mi < NMAT; ++mi) {
+        const int mat = wv + NW * mi;
+        const double* A1 = S.buf + kTOff + ((mat >> 1) * 2) * (M * kLd);
         const double* A2 = A1 + M * kLd;
-        const bool odd = wv & 1;
+        const bool odd = mat & 1;
 #pragma unroll
         for (int tile = 0; tile < 4; ++tile) {
             const int ti = tile >> 1, tj = tile & 1;
@@ -190,22 +242,24 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c, 0, 0, 0);
                 c = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, c, 0, 0, 0);
             }
-            acc[tile] = c;
+            acc[mi][tile] = c;
         }
     }
     __syncthreads();  // T no longer read
     double* Wd = S.buf;         // weight spectrum, rows duplicated: [64][32] complex
     double* Rl = S.buf + 4096;  // residual spectrum [32][32] complex
-    {
-        const int part = wv & 1;  // 0 = real, 1 = imaginary
+#pragma unroll
+    for (int mi = 0; mi < NMAT; ++mi) {
+        const int mat = wv + NW * mi;
+        const int part = mat & 1;  // 0 = real, 1 = imaginary
 #pragma unroll
         for (int tile = 0; tile < 4; ++tile) {
             const int ti = tile >> 1, tj = tile & 1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int k = ti * 16 + lk + 4 * r, l = tj * 16 + li;
-                const double v = acc[tile][r];
-                if (wv < 2) {
+                const double v = acc[mi][tile][r];
+                if (mat < 2) {
                     Rl[(k * 32 + l) * 2 + part] = v;
                 } else {
                     Wd[(k * 32 + l) * 2 + part] = v;
@@ -217,69 +271,65 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     __syncthreads();
 
     // ---- K greedy steps ----------------------------------------------------
+    // thread t holds spectrum elements t + NT j (row k0 + RS j, column l)
     const int k0 = t >> 5, l = t & 31;
-    double rr[4], ri[4];
+    double rr[EPT], ri[EPT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        rr[j] = Rl[((k0 + 8 * j) * 32 + l) * 2];
-        ri[j] = Rl[((k0 + 8 * j) * 32 + l) * 2 + 1];
+    for (int j = 0; j < EPT; ++j) {
+        rr[j] = Rl[((k0 + RS * j) * 32 + l) * 2];
+        ri[j] = Rl[((k0 + RS * j) * 32 + l) * 2 + 1];
     }
     const bool live = W0 > 0.0;
+    const double g = live ? a.gamma / W0 : 0.0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
     for (int it = 0; it < K && live; ++it) {
-        // local maximiser (elements are visited in increasing index order)
-        double be = rr[0] * rr[0] + ri[0] * ri[0];
-        int bj = 0;
+        // local maximiser: strict '>' over increasing j keeps the first index
+        double lm = rr[0] * rr[0] + ri[0] * ri[0];
+        int jl = 0;
 #pragma unroll
-        for (int j = 1; j < 4; ++j) {
+        for (int j = 1; j < EPT; ++j) {
             const double e = rr[j] * rr[j] + ri[j] * ri[j];
-            if (e > be) {
-                be = e;
-                bj = j;
-            }
+            const bool take = e > lm;
+            lm = take ? e : lm;
+            jl = take ? j : jl;
         }
-        int bidx = (k0 + 8 * bj) * 32 + l;
-        double we = be;
-        int widx = bidx;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double oe = __shfl_xor(we, off);
-            const int oi = __shfl_xor(widx, off);
-            if (better(oe, oi, we, widx)) {
-                we = oe;
-                widx = oi;
-            }
+        const double wm = wave_max_nonneg(lm);
+        // the wave's first maximiser in index order (index = t + NT j)
+        const uint64_t hit = __ballot(lm == wm);
+        int wl = __ffsll((unsigned long long)hit) - 1;
+        if (__popcll(hit) > 1) {
+            // exact tie between lanes: smallest index among them
+            const int cand = (lm == wm) ? (jl * 64 + lane) : 0x7fffffff;
+            int best = cand;
+            for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
+            wl = best & 63;
         }
         const int p = it & 1;
-        if (bidx == widx) {  // the lane that owns the wave's maximiser publishes it
+        if (lane == wl) {
             double vr = rr[0], vi = ri[0];
 #pragma unroll
-            for (int j = 1; j < 4; ++j)
-                if (bj == j) {
-                    vr = rr[j];
-                    vi = ri[j];
-                }
-            S.se[p][wv] = we;
-            S.sidx[p][wv] = widx;
-            S.sr[p][wv] = vr;
-            S.si[p][wv] = vi;
-        }
-        __syncthreads();
-        double E = S.se[p][0];
-        int IDX = S.sidx[p][0];
-        double Rr = S.sr[p][0], Ri = S.si[p][0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            const double e = S.se[p][q];
-            const int i = S.sidx[p][q];
-            if (better(e, i, E, IDX)) {
-                E = e;
-                IDX = i;
-                Rr = S.sr[p][q];
-                Ri = S.si[p][q];
+            for (int j = 1; j < EPT; ++j) {
+                vr = (jl == j) ? rr[j] : vr;
+                vi = (jl == j) ? ri[j] : vi;
             }
+            S.sl[p][wv] = make_double4(wm, vr, vi, (double)(t + NT * jl));
         }
-        const double ar = a.gamma * Rr / W0;
-        const double ai = a.gamma * Ri / W0;
+        __syncthreads();  // slot visible to every lane (a single wave keeps LDS order)
+        double4 c[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) c[q] = S.sl[p][q];
+        double E = c[0].x, Rr = c[0].y, Ri = c[0].z, fi = c[0].w;
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const bool take = (c[q].x > E) | ((c[q].x == E) & (c[q].w < fi));
+            E = take ? c[q].x : E;
+            Rr = take ? c[q].y : Rr;
+            Ri = take ? c[q].z : Ri;
+            fi = take ? c[q].w : fi;
+        }
+        const int IDX = (int)fi;
+        const double ar = g * Rr;
+        const double ai = g * Ri;
         if (t == 0) {
             S.cidx[it] = IDX;
             S.car[it] = ar;
@@ -289,42 +339,44 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         const int u = IDX >> 5, v = IDX & 31;
         const double* wrow = Wd + (((k0 - u + 32) * 32 + ((l - v) & 31)) * 2);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double wr = wrow[j * 8 * 32 * 2];
-            const double wi = wrow[j * 8 * 32 * 2 + 1];
-            rr[j] -= ar * wr - ai * wi;
-            ri[j] -= ar * wi + ai * wr;
+        for (int j = 0; j < EPT; ++j) {
+            const double wr = wrow[j * RS * 32 * 2];
+            const double wi = wrow[j * RS * 32 * 2 + 1];
+            rr[j] = fma(-ar, wr, fma(ai, wi, rr[j]));
+            ri[j] = fma(-ar, wi, fma(-ai, wr, ri[j]));
         }
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
     __syncthreads();
 
     // ---- synthesis at the block's lost pixels ------------------------------
-    // B*B pixels, (256 / B^2) threads per pixel, each summing every g-th step
+    // gs threads per pixel, each summing every gs-th step; B*B pixels
     const int npx = B * B;
-    const int g = kThreads / npx;  // 16 (B=4), 4 (B=8), 1 (B=16)
-    const int px = t / g, sub = t % g;
-    const int py = px / B, pxx = px % B;
-    const int m = b + py, n = b + pxx;
-    double val = 0.0;
-    if (live) {
-        for (int it = sub; it < K; it += g) {
-            const int idx = S.cidx[it];
-            const int u = idx >> 5, v = idx & 31;
-            const int ph = (u * m + v * n) & 31;
-            val += S.car[it] * S.twc[ph] - S.cai[it] * S.tws[ph];
+    const int gs = npx >= NT ? 1 : NT / npx;
+    const int sub = t % gs;
+    for (int px = t / gs; px < npx; px += NT / gs) {
+        const int py = px / B, pxx = px % B;
+        const int m = b + py, n = b + pxx;
+        double val = 0.0;
+        if (live) {
+            for (int it = sub; it < K; it += gs) {
+                const int idx = S.cidx[it];
+                const int u = idx >> 5, v = idx & 31;
+                const int ph = (u * m + v * n) & 31;
+                val += S.car[it] * S.twc[ph] - S.cai[it] * S.tws[ph];
+            }
         }
-    }
-    for (int off = g >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
-    if (sub == 0) {
-        const int y = d.x + py, x = d.y + pxx;
-        if (y < J.H && x < J.W) {
-            const int64_t q = (int64_t)y * J.W + x;
-            if (J.status[q] == kLost) {
-                J.recon[q] = val;
-                J.status[q] = kRecon;
-                if (y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
-                    J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
+        for (int off = gs >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
+        if (sub == 0) {
+            const int y = d.x + py, x = d.y + pxx;
+            if (y < J.H && x < J.W) {
+                const int64_t q = (int64_t)y * J.W + x;
+                if (J.status[q] == kLost) {
+                    J.recon[q] = val;
+                    J.status[q] = kRecon;
+                    if (y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
+                        J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
+                }
             }
         }
     }
@@ -337,6 +389,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
 // dependency wait: every earlier block whose lost pixels meet this block's
 // window, or whose window meets this block's lost pixels
 // ---------------------------------------------------------------------------
+template <int NT>
 __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
     const int4 d = J.desc[blk];
     const int4 lb = J.lbox[blk];
@@ -352,7 +405,7 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
     // window of j
     const int jwy0 = d.x - Cj.b, jwx0 = d.y - Cj.b;
     const int jwy1 = d.x + Cj.B + Cj.b, jwx1 = d.y + Cj.B + Cj.b;
-    for (int c = threadIdx.x; c < ncell; c += kThreads) {
+    for (int c = threadIdx.x; c < ncell; c += NT) {
         const int fy = fy0 + c / nw, fx = fx0 + c % nw;
         const int i = J.owner[fy * J.fw + fx];
         if (i < 0 || i >= blk) continue;
@@ -386,7 +439,8 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
 // block kernel: tickets in dispatch order; with counter != null the grid is
 // persistent and workgroups draw tickets until none is left
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_fse_blocks(LaunchArgs a, int ticket_base) {
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Shared32& S = *reinterpret_cast<Shared32*>(smem_raw);
     const int t = threadIdx.x;
@@ -415,8 +469,8 @@ __global__ void __launch_bounds__(kThreads) k_fse_blocks(LaunchArgs a, int ticke
         const int job = S.job, blk = S.blk;
         if (job < 0) break;
         const JobDev& J = a.jobs[job];
-        wait_predecessors(a, J, blk, S);
-        process_block32(a, J, blk, S);
+        wait_predecessors<64 * NW>(a, J, blk, S);
+        process_block32<NW>(a, J, blk, S);
         __syncthreads();
         if (t == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -427,29 +481,46 @@ __global__ void __launch_bounds__(kThreads) k_fse_blocks(LaunchArgs a, int ticke
     }
 }
 
+template <int NW>
+static const void* kernel_ptr() {
+    return (const void*)k_fse_blocks<NW>;
+}
+
+static const void* kernel_for(int nw) {
+    switch (nw) {
+        case 1: return kernel_ptr<1>();
+        case 2: return kernel_ptr<2>();
+        default: return kernel_ptr<4>();
+    }
+}
+
 size_t shared_bytes_blocks() { return sizeof(Shared32); }
 
-int persistent_grid() {
+int persistent_grid(int nw) {
     int dev = 0, cus = 0, per_cu = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    hipFuncSetAttribute((const void*)k_fse_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)sizeof(Shared32));
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fse_blocks, kThreads, sizeof(Shared32)) !=
-            hipSuccess ||
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const void* k = kernel_for(nw);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * nw, sizeof(Shared32)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return std::max(1, cus) * per_cu;
 }
 
-hipError_t launch_blocks_at(const LaunchArgs& a, int grid, int ticket_base, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute((const void*)k_fse_blocks, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sizeof(Shared32));
-        attr_set = true;
+hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int grid, int ticket_base, hipStream_t st) {
+    const void* k = kernel_for(nw);
+    static bool attr_set[5] = {false, false, false, false, false};
+    if (!attr_set[nw]) {
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
+        attr_set[nw] = true;
     }
-    hipLaunchKernelGGL(k_fse_blocks, dim3(grid), dim3(kThreads), sizeof(Shared32), st, a, ticket_base);
+    if (nw == 1)
+        hipLaunchKernelGGL(k_fse_blocks<1>, dim3(grid), dim3(64), sizeof(Shared32), st, a, ticket_base);
+    else if (nw == 2)
+        hipLaunchKernelGGL(k_fse_blocks<2>, dim3(grid), dim3(128), sizeof(Shared32), st, a, ticket_base);
+    else
+        hipLaunchKernelGGL(k_fse_blocks<4>, dim3(grid), dim3(256), sizeof(Shared32), st, a, ticket_base);
     return hipGetLastError();
 }
 

@@ -25,13 +25,17 @@ struct Workspace {
     std::mutex mu;
     DevBuf recon, status, owner, desc, lbox, done, tickets, jobs, misc, tabs;
     std::vector<double> tab_key;  // parameters the uploaded tables were built for
+    uint8_t* host_mask = nullptr;  // pinned staging for mask read-back
+    size_t host_mask_cap = 0;
     hipStream_t last_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the block kernel(s) of the last call
+    bool timed = false;
     void free_all();
 };
 
 fse_status_t from_hip(hipError_t e);
 Workspace* workspace_for(hipStream_t st);
 void release_all_workspaces();
-int persistent_grid();  // resident workgroups of the block kernel on the current device
+int persistent_grid(int nw);  // resident workgroups of the block kernel (nw waves) on the current device
 
 }  // namespace fse

@@ -60,14 +60,15 @@ class fse_params_t(ctypes.Structure):
         ("rho", ctypes.c_double), ("gamma", ctypes.c_double), ("recon_weight", ctypes.c_double),
         ("precision", ctypes.c_int32), ("schedule", ctypes.c_int32), ("tiling", ctypes.c_int32),
         ("n_tiles", ctypes.c_int32), ("overlap", ctypes.c_int32), ("align", ctypes.c_int32),
-        ("workgroups", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32), ("block_waves", ctypes.c_int32),
         ("trace_sel", ctypes.c_void_p), ("trace_stride", ctypes.c_int32), ("trace_capacity", ctypes.c_int64),
     ]
 
 
 class fse_run_stats_t(ctypes.Structure):
     _fields_ = [("n_blocks", ctypes.c_int64), ("n_lost_pixels", ctypes.c_int64), ("n_degenerate", ctypes.c_int64),
-                ("n_jobs", ctypes.c_int64), ("wavefront_keys", ctypes.c_int32), ("host_plan_ms", ctypes.c_double)]
+                ("n_jobs", ctypes.c_int64), ("wavefront_keys", ctypes.c_int32), ("host_plan_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("device_error", ctypes.c_int32)]
 
 
 class fse_serve_config_t(ctypes.Structure):

@@ -90,6 +90,11 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-block comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--block-waves", type=int, default=4)
+    ap.add_argument("--tiles", type=str, default="64",
+                    help="comma-separated tile counts for the tile-framework comparison ('' = none)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 256 MiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method's tiles are "
@@ -101,8 +106,15 @@ def main():
 
     from paper_2207_00238_amd import fse, synth
 
-    wl = synth.workload(args.workload)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    wl = synth.workload(args.workload)
     img = torch.from_numpy(wl.image).to(dev)
     msk = torch.from_numpy(wl.mask).to(dev)
     out = torch.empty_like(img)
@@ -110,7 +122,7 @@ def main():
     B, b, K = wl.classes[-1]
     M = B + 2 * b
     params = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma, recon_weight=wl.recon_weight,
-                                    workgroups=args.workgroups)
+                                    workgroups=args.workgroups, block_waves=args.block_waves)
 
     for _ in range(args.warmup):
         fse.fse_extrapolate(img, msk, params, out, stream)
@@ -165,6 +177,36 @@ def main():
                      "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": traffic,
                      "kernel": "k_fse_blocks", "flops_per_block": flops},
     }
+
+    if args.tiles:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        m = torch.from_numpy(wl.mask).bool()
+        gt = torch.from_numpy(wl.image).double()
+
+        def psnr(x):
+            e = (x.double().clamp(0, 255) - gt)[m]
+            return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
+
+        p_whole = psnr(res_persistent.cpu())
+        result["psnr_whole_db"] = p_whole
+        result["tiled"] = []
+        for N in [int(v) for v in args.tiles.split(",") if v]:
+            pt = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma, recon_weight=wl.recon_weight,
+                                        tiling=fse.FSE_TILED, n_tiles=N, overlap=32, align=16,
+                                        block_waves=args.block_waves)
+            fse.fse_extrapolate(img, msk, pt, out, stream)
+            fse.fse_last_stats()
+            times = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                fse.fse_extrapolate(img, msk, pt, out, stream)
+                s = fse.fse_last_stats()
+                times.append(time.perf_counter() - t0)
+            dt = float(np.mean(times))
+            result["tiled"].append({"n_tiles": N, "overlap": 32, "value": n_blocks / dt, "unit": "blocks/s",
+                                    "ms_per_step": dt * 1e3, "kernel_ms": s["kernel_ms"],
+                                    "blocks_executed": s["n_blocks"],
+                                    "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole})
 
     if not args.no_plain:
         p_plain = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma,

@@ -143,7 +143,9 @@ fse_status_t fse_params_default(fse_params_t* p);
  * Compact tiling, Algorithm 1 with eqs. (1)-(5) of Sec. III, plus the stripe
  * d of Sec. III.  tiles: caller-owned host array of N entries.  align > 1
  * moves every interior tile edge down to a multiple of align (the block grid)
- * so that the blocks of a tile coincide with those of the image.
+ * so that the blocks of a tile coincide with those of the image.  For large
+ * N the row heights of eq. (4) add up to more than H; rows are then clipped
+ * at the bottom edge, and tiles of rows past it are empty (w or h = 0).
  * Errors: INVALID_ARG when W, H, N < 1, d < 0, align < 1 or N > W*H.
  */
 fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align,

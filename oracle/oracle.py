@@ -188,7 +188,8 @@ def tiling(W: int, H: int, N: int):
     swapped back.  eq. (1) r = W / H; eq. (2) n_R = max(1, round(sqrt(N / r)));
     eq. (3) n_C per row i (1-based): ceil(N / n_R) for i <= N mod n_R, else
     floor; eq. (4) h_T = floor(H n_C / N) + floor(((H n_C) mod N) / n_R), the
-    last row taking the rest of the height; eq. (5) w_T per tile j (1-based):
+    last row taking the rest of the height (rows clipped at the image bottom,
+    see below); eq. (5) w_T per tile j (1-based):
     ceil(W / n_C) for j <= W mod n_C, else floor.  Offsets accumulate.
     sqrt(N / r) is rounded exactly: round(sqrt(q)) = k  iff
     (k - 1/2)^2 <= q < (k + 1/2)^2.
@@ -211,6 +212,10 @@ def tiling(W: int, H: int, N: int):
         h_T = (H * n_C) // N + ((H * n_C) % N) // n_R
         if i == n_R:
             h_T = H - y_T
+        # eq. (4) can overshoot H when N is large (the second term adds up to
+        # (N - 1) / n_R per row); rows are clipped at the image bottom, so
+        # rows past it are empty
+        h_T = max(0, min(h_T, H - y_T))
         x_T = 0
         for j in range(1, n_C + 1):
             if j <= W % n_C:

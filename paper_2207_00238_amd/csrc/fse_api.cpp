@@ -472,6 +472,10 @@ fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t 
             x1 = (x1 == W) ? W : x1 / align * align;
             y1 = (y1 == H) ? H : y1 / align * align;
         }
+        x1 = std::min(x1, W);
+        y1 = std::min(y1, H);
+        x = std::min(x, x1);
+        y = std::min(y, y1);
         fse_tile_t& T = tiles[i];
         T.x = x;
         T.y = y;
@@ -479,8 +483,8 @@ fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t 
         T.h = y1 - y;
         T.ox = std::max(0, x - d);
         T.oy = std::max(0, y - d);
-        T.ow = std::min(W, x1 + d) - T.ox;
-        T.oh = std::min(H, y1 + d) - T.oy;
+        T.ow = std::max(0, std::min(W, x1 + d) - T.ox);
+        T.oh = std::max(0, std::min(H, y1 + d) - T.oy);
     }
     return FSE_OK;
 }

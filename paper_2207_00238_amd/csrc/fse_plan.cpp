@@ -146,6 +146,9 @@ bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
         // eq. (4): row height; the last row takes what is left
         int64_t hT = (Hl * nC) / N + ((Hl * nC) % N) / nR;
         if (i == nR) hT = Hl - yT;
+        // for large N eq. (4) overshoots the image height; rows are clipped at
+        // the bottom edge and rows past it stay empty
+        hT = std::max<int64_t>(0, std::min<int64_t>(hT, Hl - yT));
         int64_t xT = 0;
         for (int64_t j = 1; j <= nC; ++j) {
             // eq. (5): tile width

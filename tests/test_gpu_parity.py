@@ -127,3 +127,72 @@ def test_repeat_calls_are_deterministic():
     b, _, _ = _run(wl.image, wl.mask, wl.classes, workgroups=7)
     c, _, _ = _run(wl.image, wl.mask, wl.classes, schedule=1)
     assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def _run_tiled(img, mask, classes, N, d, align, **kw):
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    ti = torch.from_numpy(np.ascontiguousarray(img, dtype=np.float32)).to(dev)
+    tm = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).to(dev)
+    out = torch.full_like(ti, -12345.0)
+    p = fse.fse_params_default(classes=classes, tiling=fse.FSE_TILED, n_tiles=N, overlap=d, align=align, **kw)
+    fse.fse_extrapolate(ti, tm, p, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), fse.fse_last_stats()
+
+
+@pytest.mark.parametrize("N,d", [(4, 16), (7, 32), (16, 32)])
+def test_tiled_matches_tile_oracle(N, d):
+    img = synth.synth_image(200, 136, seed=41, period_max=128.0)
+    mask = synth.mask_blocks_and_pixels(200, 136, 4, 0.25, 0.01, seed=42)
+    cls = ((4, 14, 60),)
+    ref = O.image_tiled(img, mask, cls, N, d, 16)
+    got, st = _run_tiled(img, mask, cls, N, d, 16)
+    assert st["n_jobs"] == N
+    m = mask.astype(bool)
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got - ref)[m].max() <= TIGHT
+
+
+def test_tiled_equals_whole_for_isolated_losses():
+    # losses farther apart than the support: tiles with d >= border change nothing
+    img = synth.synth_image(192, 160, seed=43)
+    mask = np.zeros((160, 192), np.uint8)
+    for (y, x) in [(20, 20), (20, 100), (80, 60), (120, 150), (100, 176), (140, 8)]:
+        mask[y:y + 4, x:x + 4] = 1
+    cls = ((4, 14, 100),)
+    whole, _, _ = _run(img, mask, cls)
+    tiled, _ = _run_tiled(img, mask, cls, 6, 32, 16)
+    m = mask.astype(bool)
+    assert np.abs(whole - tiled)[m].max() <= TIGHT
+
+
+def test_batch_of_images_matches_each_oracle():
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    cases = [(96, 80, 51), (130, 70, 53), (64, 64, 55)]
+    ims, mks, outs, refs = [], [], [], []
+    cls = ((4, 14, 50),)
+    for (W, H, sd) in cases:
+        img = synth.synth_image(W, H, seed=sd)
+        mask = synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=sd + 1)
+        refs.append((img, mask, O.image(img, mask, cls)))
+        ims.append(torch.from_numpy(img).to(dev))
+        mks.append(torch.from_numpy(mask).to(dev))
+        outs.append(torch.empty_like(ims[-1]))
+    p = fse.fse_params_default(classes=cls)
+    fse.fse_extrapolate_batch(ims, mks, p, outs)
+    torch.cuda.synchronize()
+    for (img, mask, ref), o in zip(refs, outs):
+        got = o.cpu().numpy()
+        m = mask.astype(bool)
+        assert np.array_equal(got[~m], img[~m])
+        assert np.abs(got - ref)[m].max() <= TIGHT
+
+
+@pytest.mark.parametrize("nw", [1, 2])
+def test_block_wave_variants(nw):
+    wl = synth.workload("small")
+    _check(wl.image, wl.mask, wl.classes, block_waves=nw)

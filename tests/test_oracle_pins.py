@@ -210,3 +210,31 @@ def test_degenerate_block_without_support():
     out, tr = O.image(img, mask, ((4, 6, 3),), trace=True)
     assert tr["degenerate"]
     assert (out == 0).all()
+
+
+def test_tiles_equal_whole_for_isolated_losses_oracle():
+    # the tile framework reproduces the whole-image result when every loss is
+    # farther from a tile seam and from other losses than the support reaches
+    img = synth.synth_image(192, 160, seed=43)
+    mask = np.zeros((160, 192), np.uint8)
+    for (y, x) in [(20, 20), (20, 100), (80, 60), (120, 150), (100, 176), (140, 8)]:
+        mask[y:y + 4, x:x + 4] = 1
+    cls = ((4, 14, 100),)
+    whole = O.image(img, mask, cls)
+    tiled = O.image_tiled(img, mask, cls, 6, 32, 16)
+    assert np.array_equal(whole, tiled)
+
+
+def test_tiles_differ_slightly_for_dense_losses_oracle():
+    # dense losses: blocks in a tile's stripe see a clipped support, so the
+    # tiled result differs from the whole image, by little (the magnitude
+    # the paper reports is a few hundredths of a dB)
+    img = synth.synth_image(160, 128, seed=44)
+    mask = synth.mask_blocks(160, 128, 4, 0.3, seed=45)
+    cls = ((4, 14, 40),)
+    whole = O.image(img, mask, cls)
+    tiled = O.image_tiled(img, mask, cls, 4, 32, 16)
+    m = mask.astype(bool)
+    from parity import psnr
+    d = abs(psnr(whole, img, m) - psnr(tiled, img, m))
+    assert d < 0.5

@@ -86,3 +86,14 @@ def test_stripe_and_alignment():
         assert ex + ew == min(W, x + w + 32) and ey + eh == min(H, y + h + 32)
     cov = _cover(W, H, [c for c, _ in O.tiles_with_stripe(W, H, 16, 32, align=16)])
     assert (cov == 1).all()
+
+
+@pytest.mark.parametrize("W,H,N", [(1920, 1080, 256), (1920, 1080, 1024), (3840, 2160, 4096), (640, 480, 300)])
+def test_large_n_rows_clipped_still_partition(W, H, N):
+    # eq. (4) overshoots H for these N; with the rows clipped at the bottom the
+    # tiles still cover the image exactly once and none has a negative size
+    tiles = O.tiling(W, H, N)
+    assert len(tiles) == N
+    assert all(t[2] >= 0 and t[3] >= 0 for t in tiles)
+    cov = _cover(W, H, tiles)
+    assert (cov == 1).all()

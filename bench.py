@@ -124,7 +124,7 @@ def main():
     params = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma, recon_weight=wl.recon_weight,
                                     workgroups=args.workgroups, block_waves=args.block_waves)
 
-    for _ in range(args.warmup):
+    for _ in range(max(args.warmup, 1)):
         fse.fse_extrapolate(img, msk, params, out, stream)
     torch.cuda.synchronize()
     st = fse.fse_last_stats()

@@ -1,17 +1,20 @@
 """Benchmark: lost processing blocks per second of Frequency Selective
 Extrapolation on one MI355X.
 
-Workload (default ``hd``): one 1920x1080 synthetic luma image, 25 % of the
-4x4 blocks lost plus 1 % isolated defect pixels, 32x32 support and DFT,
-K = 100, rho = 0.8, gamma = 0.5, recon weight 0.5, FP64 arithmetic.
+Workload: 1920x1080 synthetic luma requests, 25 % of the 4x4 blocks lost
+plus 1 % isolated defect pixels, 32x32 support and DFT, K = 100, rho = 0.8,
+gamma = 0.5, recon weight 0.5, FP64 arithmetic, exact raster semantics per
+request.
 
-A step is one complete ``fse_extrapolate`` call on inputs already resident in
-HBM: host planning of the blocks and their dependency order, upload of the
-plan, and the persistent dependency-driven kernel that runs every block.
-``value`` = processing blocks per second over the timed steps.  The plain
-GPU path (one kernel launch per block, raster order) is timed once on the
-same input for comparison, and the FP64 CPU oracle is timed on a bounded
-sample of the same workload.
+A step is one batched extrapolation of ``--batch`` requests on inputs already
+resident in HBM: host planning of every request's blocks and dependency
+order, upload of the plan, and one persistent dependency-driven kernel that
+runs the blocks of all requests.  ``value`` = processing blocks per second
+over the timed steps.  Also reported: one request alone, the paper's tile
+framework on one request, a served Poisson stream of requests (continuous
+batching, p50/p99 latency), the plain GPU path (one kernel launch per block,
+raster order; bitwise-identical output), and the FP64 CPU oracle on a
+bounded sample.
 
 Prints one JSON line.
 """
@@ -60,16 +63,17 @@ def traffic_from_profiles(workload: str, n_launch_units: float):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(seconds_budget: float = 20.0):
-    """The FP64 oracle, single thread, on the top-left 256x256 crop of the
-    workload's image and mask (the crop is processed as an image of its own)."""
+def cpu_baseline():
+    """The FP64 oracle, single thread, on the top-left 640x480 crop of the
+    workload's first image and mask (the crop is processed as an image of its
+    own)."""
     import numpy as np
 
     from oracle import oracle
     from paper_2207_00238_amd import synth
 
     wl = synth.workload("hd")
-    crop = (320, 320)
+    crop = (480, 640)
     img = wl.image[:crop[0], :crop[1]]
     msk = wl.mask[:crop[0], :crop[1]]
     nb = len(oracle.plan(msk, wl.classes)[0])
@@ -77,7 +81,7 @@ def cpu_baseline(seconds_budget: float = 20.0):
     oracle.image(img, msk, wl.classes, rho=wl.rho, gamma=wl.gamma, delta=wl.recon_weight)
     dt = time.perf_counter() - t0
     return {"value": nb / dt, "unit": "blocks/s", "cores": 1, "kind": "oracle",
-            "sample": f"top-left {crop[1]}x{crop[0]} crop of the 1920x1080 workload ({nb} blocks, {dt:.1f} s, "
+            "sample": f"top-left {crop[1]}x{crop[0]} crop of the first 1920x1080 request ({nb} blocks, {dt:.1f} s, "
                       f"single-threaded FP64 C oracle)"}
 
 
@@ -86,13 +90,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="hd", choices=["hd", "small"])
+    ap.add_argument("--batch", type=int, default=8, help="1920x1080 requests per batched step")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-block comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--block-waves", type=int, default=4)
     ap.add_argument("--tiles", type=str, default="64",
                     help="comma-separated tile counts for the tile-framework comparison ('' = none)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="length of the served Poisson stream (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=16.0, help="requests per second of the served stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -114,28 +120,31 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    wl = synth.workload(args.workload)
-    img = torch.from_numpy(wl.image).to(dev)
-    msk = torch.from_numpy(wl.mask).to(dev)
-    out = torch.empty_like(img)
+
+    n_img = max(1, args.batch)
+    wls = [synth.workload("hd", i) for i in range(n_img)]
+    wl = wls[0]
+    imgs = [torch.from_numpy(w.image).to(dev) for w in wls]
+    msks = [torch.from_numpy(w.mask).to(dev) for w in wls]
+    outs = [torch.empty_like(t) for t in imgs]
     stream = torch.cuda.current_stream()
     B, b, K = wl.classes[-1]
     M = B + 2 * b
-    params = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma, recon_weight=wl.recon_weight,
-                                    workgroups=args.workgroups, block_waves=args.block_waves)
+    common = dict(classes=wl.classes, rho=wl.rho, gamma=wl.gamma, recon_weight=wl.recon_weight,
+                  workgroups=args.workgroups, block_waves=args.block_waves)
+    params = fse.fse_params_default(**common)
 
+    # ---- batched step: n_img requests in one persistent launch -------------
     for _ in range(max(args.warmup, 1)):
-        fse.fse_extrapolate(img, msk, params, out, stream)
-    torch.cuda.synchronize()
+        fse.fse_extrapolate_batch(imgs, msks, params, outs, stream)
     st = fse.fse_last_stats()
     n_blocks = st["n_blocks"]
-
     step_ms, kern_ms, plan_ms = [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        fse.fse_extrapolate(img, msk, params, out, stream)
+        fse.fse_extrapolate_batch(imgs, msks, params, outs, stream)
         s = fse.fse_last_stats()  # waits for the step's stream
         step_ms.append((time.perf_counter() - t0) * 1e3)
         kern_ms.append(s["kernel_ms"])
@@ -145,12 +154,12 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
     value = n_blocks * args.steps / total
-    res_persistent = out.clone()
+    batched_out0 = outs[0].clone()
 
     flops = block_flops(M, K, B)
     k_avg = float(np.mean(kern_ms)) / 1e3
     achieved = n_blocks * flops / k_avg / 1e12
-    traffic = traffic_from_profiles(args.workload, n_blocks)
+    traffic = traffic_from_profiles("hd", n_blocks)
 
     result = {
         "metric": "lost 4x4 blocks/s at K=100 (batched+served vs plain GPU, same acc.); p50/p99 ms",
@@ -165,21 +174,36 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl.image.shape[1]}x{wl.image.shape[0]}, "
-                               f"{n_blocks} processing blocks, B={B} b={b} M={M} K={K}, rho={wl.rho}, "
-                               f"gamma={wl.gamma}, whole image, exact raster semantics",
-                   "schedule": "persistent dependency-driven kernel"},
-        "p50_ms": float(np.percentile(step_ms, 50)),
-        "p99_ms": float(np.percentile(step_ms, 99)),
+        "config": {"workload": f"hd: {n_img} requests of 1920x1080, 25% 4x4 blocks + 1% pixels lost, "
+                               f"{n_blocks} processing blocks per step, B={B} b={b} M={M} K={K}, rho={wl.rho}, "
+                               f"gamma={wl.gamma}, exact raster semantics per request",
+                   "schedule": f"one persistent dependency-driven launch per step, {args.block_waves} waves/block"},
+        "step_p50_ms": float(np.percentile(step_ms, 50)),
+        "step_p99_ms": float(np.percentile(step_ms, 99)),
         "kernel_ms": float(np.mean(kern_ms)),
         "host_plan_ms": float(np.mean(plan_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": traffic,
-                     "kernel": "k_fse_blocks", "flops_per_block": flops},
+                     "kernel": f"k_fse_blocks<{args.block_waves}>", "flops_per_block": flops},
     }
 
+    # ---- one request alone ------------------------------------------------
+    img, msk, out = imgs[0], msks[0], outs[0]
+    fse.fse_extrapolate(img, msk, params, out, stream)
+    s = fse.fse_last_stats()
+    times = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        fse.fse_extrapolate(img, msk, params, out, stream)
+        s1 = fse.fse_last_stats()
+        times.append(time.perf_counter() - t0)
+    nb1 = s1["n_blocks"]
+    res_single = out.clone()
+    result["single_request"] = {"value": nb1 / float(np.mean(times)), "unit": "blocks/s",
+                                "ms": float(np.mean(times)) * 1e3, "kernel_ms": s1["kernel_ms"],
+                                "blocks": nb1, "bitwise_equal_to_batched": bool(torch.equal(res_single, batched_out0))}
+
     if args.tiles:
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
         m = torch.from_numpy(wl.mask).bool()
         gt = torch.from_numpy(wl.image).double()
 
@@ -187,13 +211,11 @@ def main():
             e = (x.double().clamp(0, 255) - gt)[m]
             return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
 
-        p_whole = psnr(res_persistent.cpu())
+        p_whole = psnr(res_single.cpu())
         result["psnr_whole_db"] = p_whole
         result["tiled"] = []
         for N in [int(v) for v in args.tiles.split(",") if v]:
-            pt = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma, recon_weight=wl.recon_weight,
-                                        tiling=fse.FSE_TILED, n_tiles=N, overlap=32, align=16,
-                                        block_waves=args.block_waves)
+            pt = fse.fse_params_default(tiling=fse.FSE_TILED, n_tiles=N, overlap=32, align=16, **common)
             fse.fse_extrapolate(img, msk, pt, out, stream)
             fse.fse_last_stats()
             times = []
@@ -203,28 +225,67 @@ def main():
                 s = fse.fse_last_stats()
                 times.append(time.perf_counter() - t0)
             dt = float(np.mean(times))
-            result["tiled"].append({"n_tiles": N, "overlap": 32, "value": n_blocks / dt, "unit": "blocks/s",
+            result["tiled"].append({"n_tiles": N, "overlap": 32, "value": nb1 / dt, "unit": "blocks/s",
                                     "ms_per_step": dt * 1e3, "kernel_ms": s["kernel_ms"],
                                     "blocks_executed": s["n_blocks"],
                                     "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole})
 
+    if args.serve_seconds > 0:
+        result["served"] = serve_stream(fse, torch, np, imgs, msks, params, args.serve_rate, args.serve_seconds,
+                                        nb1, res_single)
+
     if not args.no_plain:
-        p_plain = fse.fse_params_default(classes=wl.classes, rho=wl.rho, gamma=wl.gamma,
-                                         recon_weight=wl.recon_weight, schedule=fse.FSE_SCHED_PER_BLOCK)
+        p_plain = fse.fse_params_default(schedule=fse.FSE_SCHED_PER_BLOCK, **common)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fse.fse_extrapolate(img, msk, p_plain, out, stream)
         s = fse.fse_last_stats()
         dt = time.perf_counter() - t0
-        same = bool(torch.equal(out, res_persistent))
-        result["plain"] = {"value": n_blocks / dt, "unit": "blocks/s", "ms": dt * 1e3,
-                           "kernel_ms": s["kernel_ms"], "schedule": "one launch per block, raster order",
+        same = bool(torch.equal(out, res_single))
+        result["plain"] = {"value": nb1 / dt, "unit": "blocks/s", "ms": dt * 1e3,
+                           "kernel_ms": s["kernel_ms"], "schedule": "one launch per block, raster order, one request",
                            "bitwise_equal_to_batched": same}
-        result["speedup_vs_plain"] = value / (n_blocks / dt)
+        result["speedup_vs_plain"] = value / (nb1 / dt)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def serve_stream(fse, torch, np, imgs, msks, params, rate, seconds, blocks_per_req, ref0):
+    """Poisson arrivals of 1920x1080 requests (inputs cycled from a pool of
+    distinct images) into the continuous-batching server; latency = submit to
+    done on the host clock."""
+    rng = np.random.default_rng(31)
+    arrivals = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        arrivals.append(t)
+    srv = fse.fse_serve_create(hbm_budget_bytes=16 << 30, max_slots=4)
+    outs = [torch.empty_like(imgs[0]) for _ in arrivals]
+    tickets = []
+    try:
+        t0 = time.perf_counter()
+        for i, ta in enumerate(arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            k = i % len(imgs)
+            tickets.append((fse.fse_serve_submit(srv, imgs[k], msks[k], params, outs[i]), k))
+        stats = [fse.fse_serve_wait(srv, tk, 120_000_000) for tk, _ in tickets]
+        t_end = time.perf_counter()
+    finally:
+        fse.fse_serve_destroy(srv)
+    lat = np.array([s["t_done_ms"] - s["t_submit_ms"] for s in stats])
+    first0 = next(i for i, (_, k) in enumerate(tickets) if k == 0)
+    blocks = sum(s["n_blocks"] for s in stats)
+    return {"requests": len(arrivals), "rate_hz": rate, "seconds": seconds,
+            "value": blocks / (t_end - t0), "unit": "blocks/s",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "bitwise_equal_to_alone": bool(torch.equal(outs[first0], ref0))}
 
 
 if __name__ == "__main__":

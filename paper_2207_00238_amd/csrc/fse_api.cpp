@@ -420,6 +420,8 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     return FSE_OK;
 }
 
+void fse_last_stats_nowait(fse_run_stats_t* st) { *st = g_last_stats; }
+
 }  // namespace fse
 
 using namespace fse;

@@ -33,7 +33,14 @@ struct Workspace {
     void free_all();
 };
 
+struct ClassCfg;
 fse_status_t from_hip(hipError_t e);
+fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls);
+// one extrapolation call (fse_extrapolate / fse_extrapolate_batch)
+fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                       fse_image_t* outs, hipStream_t st);
+// statistics of this thread's last call as planned on the host (no device wait)
+void fse_last_stats_nowait(fse_run_stats_t* st);
 Workspace* workspace_for(hipStream_t st);
 void release_all_workspaces();
 int persistent_grid(int nw);  // resident workgroups of the block kernel (nw waves) on the current device

@@ -1,34 +1,316 @@
 // fse_serve.cpp -- continuous-batching request server of libfse.
+//
+// A server owns `max_slots` HIP streams.  Submitted requests wait in a FIFO
+// queue.  A scheduler thread repeatedly takes the requests that fit the HBM
+// budget (estimated per request from its size), groups those with identical
+// parameters, and launches each group as one batched persistent extrapolation
+// on a free stream slot.  Launches on different slots run concurrently on the
+// device, so requests that arrive while earlier ones are on the GPU join the
+// next launch and overlap with them.  A launch's completion (an event on its
+// stream) releases its budget and marks its requests done.  Results do not
+// depend on what else is in a launch: every request keeps its own working
+// state and dependency order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "../../include/fse.h"
+#include "fse_plan.h"
+#include "fse_runtime.h"
+
+namespace fse {
+
+
+static double steady_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    uint64_t ticket;
+    fse_image_t image, out;
+    fse_mask_t mask;
+    fse_params_t params;
+    int64_t bytes;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int64_t n_blocks = 0;
+    int state = 0;  // 0 queued, 1 running, 2 done, 3 failed
+    fse_status_t status = FSE_OK;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done_ev = nullptr;
+    std::vector<std::shared_ptr<Request>> reqs;
+    int64_t bytes = 0;
+    bool busy = false;
+};
+
+}  // namespace fse
+
+struct fse_server {
+    fse_serve_config_t cfg{};
+    std::mutex mu;
+    std::condition_variable cv;       // wakes the scheduler
+    std::condition_variable done_cv;  // wakes waiters
+    std::deque<std::shared_ptr<fse::Request>> queue;
+    std::map<uint64_t, std::shared_ptr<fse::Request>> all;
+    std::vector<fse::Slot> slots;
+    int64_t bytes_in_use = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+};
+
+namespace fse {
+
+// Device memory one request needs beyond its caller-owned buffers: FP64
+// reconstructed values and status per pixel, the fine-cell owner map, block
+// tables, tickets and flags (upper bounds).
+static int64_t request_bytes(const fse_image_t& im, const fse_params_t& p) {
+    const int64_t px = (int64_t)im.width * im.height;
+    int bmin = p.classes[p.n_classes - 1].block;
+    if (bmin < 1) bmin = 1;
+    const int64_t cells = ((int64_t)im.width + bmin - 1) / bmin * (((int64_t)im.height + bmin - 1) / bmin);
+    int64_t tiles_extra = 0;
+    if (p.tiling == FSE_TILED) tiles_extra = px;  // overlap stripes, generous
+    return (px + tiles_extra) * 9 + cells * (4 + 16 + 16 + 4 + 8);
+}
+
+// Requests can share a launch when every field that the kernels read agrees.
+static bool same_params(const fse_params_t& a, const fse_params_t& b) {
+    if (a.n_classes != b.n_classes || a.rho != b.rho || a.gamma != b.gamma || a.recon_weight != b.recon_weight ||
+        a.precision != b.precision || a.schedule != b.schedule || a.tiling != b.tiling || a.workgroups != b.workgroups ||
+        a.block_waves != b.block_waves)
+        return false;
+    for (int c = 0; c < a.n_classes; ++c)
+        if (a.classes[c].block != b.classes[c].block || a.classes[c].border != b.classes[c].border ||
+            a.classes[c].iters != b.classes[c].iters)
+            return false;
+    if (a.tiling == FSE_TILED && (a.n_tiles != b.n_tiles || a.overlap != b.overlap || a.align != b.align)) return false;
+    return true;
+}
+
+static void scheduler(fse_server* S) {
+    int dev = S->cfg.device;
+    (void)hipSetDevice(dev);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        // retire finished launches
+        bool any_running = false;
+        for (auto& sl : S->slots) {
+            if (!sl.busy) continue;
+            if (hipEventQuery(sl.done_ev) == hipSuccess) {
+                const double t = steady_ms();
+                for (auto& r : sl.reqs) {
+                    r->t_done = t;
+                    if (r->state == 1) r->state = 2;
+                }
+                S->bytes_in_use -= sl.bytes;
+                sl.reqs.clear();
+                sl.bytes = 0;
+                sl.busy = false;
+                S->done_cv.notify_all();
+            } else {
+                any_running = true;
+            }
+        }
+        if (S->stop && S->queue.empty() && !any_running) break;
+        // admit: FIFO, by budget, one launch per free slot, same parameters per launch
+        int free_slot = -1;
+        for (size_t i = 0; i < S->slots.size(); ++i)
+            if (!S->slots[i].busy) {
+                free_slot = (int)i;
+                break;
+            }
+        if (free_slot >= 0 && !S->queue.empty()) {
+            std::vector<std::shared_ptr<Request>> take;
+            int64_t bytes = 0;
+            const fse_params_t p0 = S->queue.front()->params;  // copy: the front may be taken below
+            for (auto it = S->queue.begin(); it != S->queue.end();) {
+                auto& r = *it;
+                if (!same_params(r->params, p0)) {
+                    ++it;
+                    continue;
+                }
+                if (S->bytes_in_use + bytes + r->bytes > S->cfg.hbm_budget_bytes) break;
+                bytes += r->bytes;
+                take.push_back(r);
+                it = S->queue.erase(it);
+            }
+            if (!take.empty()) {
+                Slot& sl = S->slots[free_slot];
+                sl.busy = true;
+                sl.reqs = take;
+                sl.bytes = bytes;
+                S->bytes_in_use += bytes;
+                const double t = steady_ms();
+                for (auto& r : take) {
+                    r->t_admit = t;
+                    r->state = 1;
+                }
+                std::vector<fse_image_t> ims, outs;
+                std::vector<fse_mask_t> mks;
+                for (auto& r : take) {
+                    ims.push_back(r->image);
+                    outs.push_back(r->out);
+                    mks.push_back(r->mask);
+                }
+                fse_params_t p = p0;
+                p.trace_sel = nullptr;
+                lk.unlock();
+                fse_status_t s = run_batch((int)take.size(), ims.data(), mks.data(), &p, outs.data(), sl.stream);
+                fse_run_stats_t st{};
+                fse_last_stats_nowait(&st);
+                if (s == FSE_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) s = FSE_ERR_DEVICE;
+                lk.lock();
+                const int64_t per = take.empty() ? 0 : st.n_blocks / (int64_t)take.size();
+                for (auto& r : take) r->n_blocks = per;
+                if (s != FSE_OK) {
+                    const double t2 = steady_ms();
+                    for (auto& r : take) {
+                        r->state = 3;
+                        r->status = s;
+                        r->t_done = t2;
+                    }
+                    S->bytes_in_use -= bytes;
+                    sl.busy = false;
+                    sl.reqs.clear();
+                    sl.bytes = 0;
+                    S->done_cv.notify_all();
+                }
+                continue;  // try to fill another slot at once
+            }
+        }
+        S->cv.wait_for(lk, std::chrono::microseconds(any_running ? 100 : 2000));
+    }
+}
+
+}  // namespace fse
+
+using namespace fse;
 
 extern "C" {
 
-struct fse_server {
-    int dummy;
-};
-
 fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** server) {
-    (void)cfg;
-    (void)server;
-    return FSE_ERR_UNSUPPORTED;
+    if (!cfg || !server || cfg->max_slots < 1 || cfg->max_slots > 16 || cfg->hbm_budget_bytes <= 0)
+        return FSE_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return FSE_ERR_INVALID_ARG;
+    auto* S = new fse_server();
+    S->cfg = *cfg;
+    if (hipSetDevice(cfg->device) != hipSuccess) {
+        delete S;
+        return FSE_ERR_DEVICE;
+    }
+    S->slots.resize(cfg->max_slots);
+    for (auto& sl : S->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess) {
+            for (auto& s2 : S->slots) {
+                if (s2.stream) (void)hipStreamDestroy(s2.stream);
+                if (s2.done_ev) (void)hipEventDestroy(s2.done_ev);
+            }
+            delete S;
+            return FSE_ERR_DEVICE;
+        }
+    }
+    S->worker = std::thread(scheduler, S);
+    *server = S;
+    return FSE_OK;
 }
-fse_status_t fse_serve_submit(fse_server_t* s, const fse_image_t* image, const fse_mask_t* mask,
+
+fse_status_t fse_serve_submit(fse_server_t* S, const fse_image_t* image, const fse_mask_t* mask,
                               const fse_params_t* p, fse_image_t* out, uint64_t* ticket) {
-    (void)s; (void)image; (void)mask; (void)p; (void)out; (void)ticket;
-    return FSE_ERR_UNSUPPORTED;
+    if (!S || !image || !mask || !p || !out || !ticket) return FSE_ERR_INVALID_ARG;
+    std::vector<ClassCfg> cls;
+    fse_status_t s = check_params(p, cls);
+    if (s != FSE_OK) return s;
+    if (!image->data || !out->data || !mask->data || image->width < 1 || image->height < 1 ||
+        mask->width != image->width || mask->height != image->height || out->width != image->width ||
+        out->height != image->height || image->pitch < image->width || out->pitch < out->width ||
+        mask->pitch < mask->width || out->data == image->data)
+        return FSE_ERR_INVALID_ARG;
+    auto r = std::make_shared<Request>();
+    r->image = *image;
+    r->mask = *mask;
+    r->out = *out;
+    r->params = *p;
+    r->params.trace_sel = nullptr;
+    r->bytes = request_bytes(*image, *p);
+    if (r->bytes > S->cfg.hbm_budget_bytes) return FSE_ERR_BUDGET;
+    r->t_submit = steady_ms();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return FSE_ERR_BUSY;
+    r->ticket = S->next_ticket++;
+    S->queue.push_back(r);
+    S->all[r->ticket] = r;
+    *ticket = r->ticket;
+    S->cv.notify_one();
+    return FSE_OK;
 }
-fse_status_t fse_serve_poll(fse_server_t* s, uint64_t ticket, int32_t* done, fse_request_stats_t* st) {
-    (void)s; (void)ticket; (void)done; (void)st;
-    return FSE_ERR_UNSUPPORTED;
+
+static void fill_stats(const Request& r, fse_request_stats_t* st) {
+    if (!st) return;
+    st->t_submit_ms = r.t_submit;
+    st->t_admit_ms = r.t_admit;
+    st->t_done_ms = r.t_done;
+    st->n_blocks = r.n_blocks;
 }
-fse_status_t fse_serve_wait(fse_server_t* s, uint64_t ticket, int64_t timeout_us, fse_request_stats_t* st) {
-    (void)s; (void)ticket; (void)timeout_us; (void)st;
-    return FSE_ERR_UNSUPPORTED;
+
+fse_status_t fse_serve_poll(fse_server_t* S, uint64_t ticket, int32_t* done, fse_request_stats_t* st) {
+    if (!S || !done) return FSE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
+    const Request& r = *it->second;
+    *done = r.state >= 2;
+    fill_stats(r, st);
+    return r.state == 3 ? r.status : FSE_OK;
 }
-fse_status_t fse_serve_destroy(fse_server_t* s) {
-    (void)s;
-    return FSE_ERR_UNSUPPORTED;
+
+fse_status_t fse_serve_wait(fse_server_t* S, uint64_t ticket, int64_t timeout_us, fse_request_stats_t* st) {
+    if (!S) return FSE_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
+    auto r = it->second;
+    auto pred = [&] { return r->state >= 2; };
+    if (timeout_us < 0) {
+        S->done_cv.wait(lk, pred);
+    } else if (!S->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), pred)) {
+        return FSE_ERR_TIMEOUT;
+    }
+    fill_stats(*r, st);
+    const fse_status_t s = r->state == 3 ? r->status : FSE_OK;
+    S->all.erase(ticket);
+    return s;
 }
+
+fse_status_t fse_serve_destroy(fse_server_t* S) {
+    if (!S) return FSE_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv.notify_all();
+    }
+    if (S->worker.joinable()) S->worker.join();
+    for (auto& sl : S->slots) {
+        (void)hipStreamSynchronize(sl.stream);
+        (void)hipStreamDestroy(sl.stream);
+        (void)hipEventDestroy(sl.done_ev);
+    }
+    delete S;
+    return FSE_OK;
 }
+
+}  // extern "C"

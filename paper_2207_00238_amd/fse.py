@@ -214,3 +214,44 @@ def extrapolate(image, mask, params: fse_params_t | None = None, stream=None):
     out = torch.empty_like(image)
     fse_extrapolate(image, mask, params if params is not None else fse_params_default(), out, stream)
     return out
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+def fse_serve_create(hbm_budget_bytes: int, max_slots: int = 4, device: int = 0, workgroups: int = 0):
+    cfg = fse_serve_config_t(hbm_budget_bytes, max_slots, device, workgroups)
+    h = ctypes.c_void_p()
+    check(lib().fse_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "fse_serve_create")
+    return h
+
+
+def fse_serve_submit(server, image, mask, params: fse_params_t, out) -> int:
+    """Queue one request; the tensors must stay alive until it is done."""
+    im, mk, ot = _image(image), _mask(mask), _image(out)
+    t = ctypes.c_uint64()
+    check(lib().fse_serve_submit(server, ctypes.byref(im), ctypes.byref(mk), ctypes.byref(params), ctypes.byref(ot),
+                                 ctypes.byref(t)), "fse_serve_submit")
+    return t.value
+
+
+def _req_stats(st) -> dict:
+    return {k: getattr(st, k) for k, _ in fse_request_stats_t._fields_}
+
+
+def fse_serve_poll(server, ticket: int):
+    done = ctypes.c_int32()
+    st = fse_request_stats_t()
+    check(lib().fse_serve_poll(server, ticket, ctypes.byref(done), ctypes.byref(st)), "fse_serve_poll")
+    return bool(done.value), _req_stats(st)
+
+
+def fse_serve_wait(server, ticket: int, timeout_us: int = -1) -> dict:
+    st = fse_request_stats_t()
+    check(lib().fse_serve_wait(server, ticket, timeout_us, ctypes.byref(st)), "fse_serve_wait")
+    return _req_stats(st)
+
+
+def fse_serve_destroy(server) -> None:
+    check(lib().fse_serve_destroy(server), "fse_serve_destroy")

@@ -127,8 +127,9 @@ def workload(name: str, index: int = 0) -> Workload:
 
     ``small``  : 128x128, sinusoid periods 4-64 px, 20 % of 4x4 blocks lost,
                  border 14 (32x32 support), K = 100.  Seeds 1 / 2.
-    ``hd``     : 1920x1080, periods 4-256 px, 25 % of 4x4 blocks lost plus
-                 1 % isolated defect pixels, border 14, K = 100.  Seeds 11 / 12.
+    ``hd``     : image ``index`` of a set of 1920x1080 frames, periods 4-256 px,
+                 25 % of 4x4 blocks lost plus 1 % isolated defect pixels,
+                 border 14, K = 100.  Seeds 11 + 2 i / 12 + 2 i.
     ``uhd``    : image ``index`` of a set of 3840x2160 frames with mixed
                  8x8 (10 %), 16x16 (5 %) and row (0.5 %) losses; 8x8 and
                  16x16 losses use a 64x64 support with K = 200, the rest
@@ -140,8 +141,8 @@ def workload(name: str, index: int = 0) -> Workload:
         msk = mask_blocks(128, 128, 4, 0.20, seed=2)
         return Workload(name, img, msk, ((4, 14, 100),))
     if name == "hd":
-        img = synth_image(1920, 1080, seed=11, period_max=256.0)
-        msk = mask_blocks_and_pixels(1920, 1080, 4, 0.25, 0.01, seed=12)
+        img = synth_image(1920, 1080, seed=11 + 2 * index, period_max=256.0)
+        msk = mask_blocks_and_pixels(1920, 1080, 4, 0.25, 0.01, seed=12 + 2 * index)
         return Workload(name, img, msk, ((4, 14, 100),))
     if name == "uhd":
         img = synth_image(3840, 2160, seed=21 + 2 * index, period_max=256.0)

@@ -84,3 +84,12 @@ def test_status_strings():
     L = fse.lib()
     for code in range(-8, 1):
         assert L.fse_status_string(code)
+
+
+def test_serve_create_rejects_bad_config():
+    L = fse.lib()
+    h = ctypes.c_void_p()
+    for cfg in [fse.fse_serve_config_t(0, 2, 0, 0), fse.fse_serve_config_t(1 << 20, 0, 0, 0),
+                fse.fse_serve_config_t(1 << 20, 99, 0, 0)]:
+        assert L.fse_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == fse.FSE_ERR_INVALID_ARG
+    assert L.fse_serve_destroy(None) == fse.FSE_ERR_INVALID_ARG

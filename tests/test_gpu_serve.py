@@ -1,0 +1,84 @@
+"""GPU tests of the continuous-batching server: every result is the same
+alone and in the mix; the budget admits, queues and rejects."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_00238_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-3
+
+
+def _inputs(W, H, seed, kind):
+    img = synth.synth_image(W, H, seed=seed)
+    if kind == "blocks":
+        mask = synth.mask_blocks(W, H, 4, 0.2, seed=seed + 1)
+    else:
+        mask = synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=seed + 1)
+    return img, mask
+
+
+def test_results_same_alone_and_in_the_mix():
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    cases = [(96, 80, 61, "blocks"), (200, 136, 63, "pixels"), (128, 128, 65, "blocks"), (64, 200, 67, "pixels"),
+             (150, 93, 69, "blocks"), (256, 160, 71, "pixels")]
+    p = fse.fse_params_default(classes=((4, 14, 60),))
+    alone = []
+    tens = []
+    for (W, H, sd, kind) in cases:
+        img, mask = _inputs(W, H, sd, kind)
+        ti = torch.from_numpy(img).to(dev)
+        tm = torch.from_numpy(mask).to(dev)
+        o = torch.empty_like(ti)
+        fse.fse_extrapolate(ti, tm, p, o)
+        torch.cuda.synchronize()
+        alone.append(o.cpu().numpy())
+        tens.append((ti, tm, torch.full_like(ti, -1.0), img, mask))
+    srv = fse.fse_serve_create(hbm_budget_bytes=1 << 30, max_slots=3)
+    try:
+        tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for (ti, tm, o, _, _) in tens]
+        stats = [fse.fse_serve_wait(srv, t, 60_000_000) for t in tickets]
+    finally:
+        fse.fse_serve_destroy(srv)
+    for (ti, tm, o, img, mask), a, st in zip(tens, alone, stats):
+        got = o.cpu().numpy()
+        assert np.array_equal(got, a), "served result differs from the alone result"
+        assert st["t_done_ms"] >= st["t_admit_ms"] >= st["t_submit_ms"] > 0
+    # one of them against the oracle as well
+    img, mask = tens[0][3], tens[0][4]
+    ref = O.image(img, mask, ((4, 14, 60),))
+    assert np.abs(alone[0] - ref)[mask.astype(bool)].max() <= TIGHT
+
+
+def test_budget_queues_and_rejects():
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    p = fse.fse_params_default(classes=((4, 14, 20),))
+    img, mask = _inputs(256, 256, 81, "blocks")
+    ti = torch.from_numpy(img).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    # budget fits about one request at a time: the rest must queue, not fail
+    srv = fse.fse_serve_create(hbm_budget_bytes=256 * 256 * 14, max_slots=2)
+    try:
+        outs = [torch.empty_like(ti) for _ in range(4)]
+        tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for o in outs]
+        stats = [fse.fse_serve_wait(srv, t, 60_000_000) for t in tickets]
+        ref = outs[0].cpu().numpy()
+        for o in outs[1:]:
+            assert np.array_equal(o.cpu().numpy(), ref)
+        # admitted one after another
+        admits = sorted(s["t_admit_ms"] for s in stats)
+        dones = sorted(s["t_done_ms"] for s in stats)
+        assert admits[1] >= dones[0] - 1e-3
+        big = torch.zeros((2048, 2048), dtype=torch.float32, device=dev)
+        bm = torch.zeros((2048, 2048), dtype=torch.uint8, device=dev)
+        with pytest.raises(fse.FseError) as ei:
+            fse.fse_serve_submit(srv, big, bm, p, torch.empty_like(big))
+        assert ei.value.status == fse.FSE_ERR_BUDGET
+    finally:
+        fse.fse_serve_destroy(srv)

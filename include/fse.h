@@ -114,7 +114,7 @@ typedef struct {
     int32_t schedule;  /* FSE_SCHED_* */
     int32_t tiling;    /* FSE_WHOLE or FSE_TILED */
     int32_t n_tiles, overlap, align; /* FSE_TILED: tiles N, stripe d, grid alignment */
-    int32_t workgroups;              /* persistent grid size; 0 = automatic */
+    int32_t workgroups;              /* persistent grid size; 0 = automatic (twice the mean blocks per wavefront key, at most the resident capacity) */
     int32_t block_waves;             /* wave64s per processing block: 1, 2 or 4; 0 = automatic */
     int32_t* trace_sel;
     int32_t trace_stride;

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/fse.h"
@@ -87,6 +88,9 @@ void Workspace::free_all() {
     for (DevBuf* b : {&recon, &status, &owner, &desc, &lbox, &done, &tickets, &jobs, &misc, &tabs}) b->release();
     tab_key.clear();
     if (host_mask) hipHostFree(host_mask);
+    if (stage) hipHostFree(stage);
+    stage = nullptr;
+    stage_cap = 0;
     host_mask = nullptr;
     host_mask_cap = 0;
     if (ev0) hipEventDestroy(ev0);
@@ -188,6 +192,26 @@ static fse_status_t upload_tables(Workspace& ws, const std::vector<ClassCfg>& cl
 }
 
 // ---------------------------------------------------------------------------
+// host parallelism for planning: fn(i) for i in [0, n) over up to 16 threads
+// ---------------------------------------------------------------------------
+template <class F>
+static void parallel_for(size_t n, F fn) {
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({n, hw, (size_t)16});
+    if (nt <= 1) {
+        for (size_t i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (size_t k = 0; k < nt; ++k)
+        th.emplace_back([&, k] {
+            for (size_t i = k; i < n; i += nt) fn(i);
+        });
+    for (auto& x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
 // the extrapolation call
 // ---------------------------------------------------------------------------
 struct HostJob {
@@ -255,10 +279,15 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
             }
         }
     }
-    for (auto& J : jobs) {
+    std::vector<uint8_t> plan_ok(jobs.size(), 1);
+    parallel_for(jobs.size(), [&](size_t j) {
+        HostJob& J = jobs[j];
         const uint8_t* mk = ws.host_mask + moff[J.img] + (size_t)J.oy * images[J.img].width + J.ox;
-        if (!plan_region(mk, images[J.img].width, J.W, J.H, cls, J.plan)) return FSE_ERR_INVALID_ARG;
-        stats.n_blocks += (int64_t)(J.plan.desc.size() / 4);
+        plan_ok[j] = plan_region(mk, images[J.img].width, J.W, J.H, cls, J.plan);
+    });
+    for (size_t j = 0; j < jobs.size(); ++j) {
+        if (!plan_ok[j]) return FSE_ERR_INVALID_ARG;
+        stats.n_blocks += (int64_t)(jobs[j].plan.desc.size() / 4);
     }
     for (auto& J : jobs) stats.n_lost_pixels += J.plan.lost_pixels;
     stats.n_jobs = (int64_t)jobs.size();
@@ -301,18 +330,38 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     if ((e = ws.jobs.ensure(jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
     if ((e = ws.misc.ensure(64)) != hipSuccess) return from_hip(e);
 
-    // host images of the tables, one upload each
-    std::vector<int32_t> h_owner(std::max<size_t>(n_cells, 1)), h_desc(std::max<size_t>(n_blk, 1) * 4),
-        h_lbox(std::max<size_t>(n_blk, 1) * 4);
-    std::vector<JobDev> h_jobs(jobs.size());
-    size_t o_pix = 0, o_cell = 0, o_blk = 0;
+    // host images of the tables in pinned staging memory, one upload each
+    const size_t b_owner = std::max<size_t>(n_cells, 1) * 4, b_desc = std::max<size_t>(n_blk, 1) * 16,
+                 b_tk = std::max<int64_t>(ntk, 1) * 8, b_jobs = jobs.size() * sizeof(JobDev);
+    const size_t o_owner = 0, o_desc = o_owner + ((b_owner + 255) & ~(size_t)255),
+                 o_lbox = o_desc + ((b_desc + 255) & ~(size_t)255), o_tk = o_lbox + ((b_desc + 255) & ~(size_t)255),
+                 o_jobs = o_tk + ((b_tk + 255) & ~(size_t)255), stage_bytes = o_jobs + b_jobs + 256;
+    if (ws.stage_cap < stage_bytes) {
+        if (ws.stage) (void)hipHostFree(ws.stage);
+        ws.stage = nullptr;
+        ws.stage_cap = 0;
+        if ((e = hipHostMalloc((void**)&ws.stage, stage_bytes, hipHostMallocDefault)) != hipSuccess) return from_hip(e);
+        ws.stage_cap = stage_bytes;
+    }
+    int32_t* h_owner = (int32_t*)(ws.stage + o_owner);
+    int32_t* h_desc = (int32_t*)(ws.stage + o_desc);
+    int32_t* h_lbox = (int32_t*)(ws.stage + o_lbox);
+    JobDev* h_jobs = (JobDev*)(ws.stage + o_jobs);
+    std::memcpy(ws.stage + o_tk, tickets.data(), (size_t)ntk * 8);
+    std::vector<size_t> off_pix(jobs.size() + 1, 0), off_cell(jobs.size() + 1, 0), off_blk(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j) {
+        off_pix[j + 1] = off_pix[j] + (size_t)jobs[j].W * jobs[j].H;
+        off_cell[j + 1] = off_cell[j] + jobs[j].plan.owner.size();
+        off_blk[j + 1] = off_blk[j] + jobs[j].plan.desc.size() / 4;
+    }
+    parallel_for(jobs.size(), [&](size_t j) {
         const HostJob& J = jobs[j];
         const size_t nb = J.plan.desc.size() / 4;
-        std::copy(J.plan.owner.begin(), J.plan.owner.end(), h_owner.begin() + o_cell);
-        std::copy(J.plan.desc.begin(), J.plan.desc.end(), h_desc.begin() + 4 * o_blk);
-        std::copy(J.plan.lbox.begin(), J.plan.lbox.end(), h_lbox.begin() + 4 * o_blk);
-        JobDev& D = h_jobs[j];
+        const size_t o_pix = off_pix[j], o_cell = off_cell[j], o_blk = off_blk[j];
+        std::copy(J.plan.owner.begin(), J.plan.owner.end(), h_owner + o_cell);
+        std::copy(J.plan.desc.begin(), J.plan.desc.end(), h_desc + 4 * o_blk);
+        std::copy(J.plan.lbox.begin(), J.plan.lbox.end(), h_lbox + 4 * o_blk);
+        JobDev D{};
         D.img = images[J.img].data;
         D.mask = masks[J.img].data;
         D.out = outs[J.img].data;
@@ -340,18 +389,16 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
         D.trace = tr ? p->trace_sel : nullptr;
         D.trace_stride = tr ? p->trace_stride : 0;
         D.trace_cap = tr ? p->trace_capacity : 0;
-        o_pix += (size_t)J.W * J.H;
-        o_cell += J.plan.owner.size();
-        o_blk += nb;
-    }
+        h_jobs[j] = D;
+    });
     auto up = [&](DevBuf& b, const void* h, size_t bytes) {
         return bytes ? hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
     };
-    if ((e = up(ws.owner, h_owner.data(), n_cells * 4)) != hipSuccess) return from_hip(e);
-    if ((e = up(ws.desc, h_desc.data(), n_blk * 16)) != hipSuccess) return from_hip(e);
-    if ((e = up(ws.lbox, h_lbox.data(), n_blk * 16)) != hipSuccess) return from_hip(e);
-    if ((e = up(ws.tickets, tickets.data(), (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
-    if ((e = up(ws.jobs, h_jobs.data(), jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.owner, h_owner, n_cells * 4)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.desc, h_desc, n_blk * 16)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.lbox, h_lbox, n_blk * 16)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.tickets, ws.stage + o_tk, (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
+    if ((e = up(ws.jobs, h_jobs, jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
 
     LaunchArgs a{};
     if ((s = upload_tables(ws, cls, p->rho, st, a)) != FSE_OK) return s;
@@ -387,7 +434,16 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     if (ntk > 0) {
         if (p->schedule == FSE_SCHED_PERSISTENT) {
             a.counter = counter;
-            int grid = p->workgroups > 0 ? p->workgroups : persistent_grid(nw);
+            // Automatic grid: about twice the average number of blocks that share
+            // a wavefront key.  A dependency chain runs fastest when its blocks
+            // do not share SIMDs with blocks that cannot start yet, so a grid
+            // much larger than the available parallelism only slows the chain.
+            int grid = p->workgroups;
+            if (grid <= 0) {
+                const int64_t par = (ntk + std::max(1, nkeys) - 1) / std::max(1, nkeys);
+                const int64_t want = std::max<int64_t>(64, ((2 * par + 63) / 64) * 64);
+                grid = (int)std::min<int64_t>(want, persistent_grid(nw));
+            }
             grid = (int)std::min<int64_t>(grid, ntk);
             e = launch_blocks_at(a, nw, grid, 0, st);
         } else if (p->schedule == FSE_SCHED_WAVEFRONT) {
@@ -407,7 +463,8 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
                     raster[2 * q + 1] = (int32_t)b;
                     ++q;
                 }
-            if ((e = up(ws.tickets, raster.data(), (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
+            std::memcpy(ws.stage + o_tk, raster.data(), (size_t)ntk * 8);
+            if ((e = up(ws.tickets, ws.stage + o_tk, (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
             for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, 1, (int)k, st);
         }
         if (e != hipSuccess) return from_hip(e);

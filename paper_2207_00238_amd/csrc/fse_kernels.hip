@@ -76,13 +76,12 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
     return ay0 < by1 && by0 < ay1 && ax0 < bx1 && bx0 < ax1;
 }
 
-// LDS layout (doubles) for M = 32: the DFT operands X (2 x 32 x 33) and the
-// stage-1 products T (4 x 32 x 33) side by side; afterwards the duplicated
-// weight spectrum (64 x 32 complex) and the residual spectrum (32 x 32
-// complex) reuse the same area.
+// LDS layout (doubles) for M = 32.  One 32 KB area holds, in turn: the DFT
+// operands X (w*s and w, 32 x 33 each); the weight spectrum with duplicated
+// rows (64 x 32 complex) during the K steps; the coefficient list for the
+// synthesis.
 constexpr int kLd = 33;  // padded row stride of the DFT operands
-constexpr int kXOff = 0, kTOff = 2 * 32 * kLd;
-constexpr int kBufDoubles = kTOff + 4 * 32 * kLd;  // 6336 doubles
+constexpr int kBufDoubles = 4096;
 constexpr int kMaxK = 256;
 
 struct Shared32 {
@@ -90,13 +89,9 @@ struct Shared32 {
     double twc[32], tws[32];
     double part[4];
     double4 sl[2][4];  // per wave: energy, Re R, Im R, index
-    int cidx[kMaxK];
-    double car[kMaxK], cai[kMaxK];
     int job, blk, wait_fail;
 };
 
-// FP64 maximum over a wave64 with DPP moves of the two 32-bit halves;
-// the result is valid in lane 63.
 // Unsigned 32-bit maximum over a wave64 with DPP; the result is valid in
 // lane 63.  Non-negative doubles order like their bit patterns, so the high
 // words of the energies order them up to ties in the high word.
@@ -135,28 +130,41 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 
 // ---------------------------------------------------------------------------
 // one M = 32 block, FP64 end to end, NW wave64 per block
+//
+// DFT dataflow: stage 1 forms T = X F (A operand X from LDS, B operand the
+// twiddles), stage 2 forms F T with the B operand taken straight from the
+// stage-1 accumulators: the FP64 MFMA output layout (row 4r + lane/16, column
+// lane%16) is the B-operand layout of the next product's k-step.  Each wave
+// owns NTI x NTJ output tiles of 16 x 16; it computes the stage-1 columns it
+// needs for both inputs (w*s and w), keeps its tiles of R in registers for
+// the K steps and writes its tiles of the weight spectrum to LDS.
 // ---------------------------------------------------------------------------
 template <int NW>
 __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
-    constexpr int NT = 64 * NW;     // threads
-    constexpr int EPT = 1024 / NT;  // spectrum elements (and window pixels) per thread
-    constexpr int RS = NT / 32;     // row step between a thread's elements
-    constexpr int NMAT = 4 / NW;    // DFT output matrices per wave
+    constexpr int NT = 64 * NW;                // threads
+    constexpr int NTJ = (NW == 1) ? 2 : 1;     // column tiles per wave
+    constexpr int NTI = (NW == 4) ? 1 : 2;     // row tiles per wave
+    constexpr int EPT = NTI * NTJ * 4;         // spectrum elements per lane
+    constexpr int NPIX = 1024 / NT;            // window pixels per thread while staging
+    constexpr int RS = NT / 32;
+    constexpr int NSLOT = (kMaxK + NT - 1) / NT;  // coefficient slots per thread
     constexpr int M = 32;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = t >> 6;
+    const int tj0 = (NW == 4) ? (wv & 1) : (NW == 2 ? wv : 0);
+    const int ti0 = (NW == 4) ? (wv >> 1) : 0;
     const int4 d = J.desc[blk];
     const ClassDev& C = a.cls[d.z];
     const int B = C.B, b = C.b, K = C.K;
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
 
     // ---- stage the window: weights and weighted values --------------------
-    double* Xs = S.buf + kXOff;    // w * s, [m][n] stride kLd
-    double* Xw = Xs + M * kLd;     // w
+    double* Xs = S.buf;         // w * s, [m][n] stride kLd
+    double* Xw = Xs + M * kLd;  // w
     double wsum = 0.0;
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
+    for (int j = 0; j < NPIX; ++j) {
         const int m = (t >> 5) + RS * j, n = t & 31;
         const int y = wy + m, x = wx + n;
         double w = 0.0, v = 0.0;
@@ -182,88 +190,70 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
 #pragma unroll
     for (int q = 1; q < NW; ++q) W0 += S.part[q];
 
-    // ---- stage 1: T = F X on the FP64 matrix cores --------------------------
-    // matrix 0: cos * (w s), 1: -sin * (w s), 2: cos * w, 3: -sin * w
+    // ---- stage 1: T(:, tj) = X F(:, tj), both inputs ------------------------
+    // F = C - i S with C[k,m] = cos(2 pi k m / M), S[k,m] = sin(2 pi k m / M)
     const int li = lane & 15, lk = lane >> 4;
-    dbl4 acc[NMAT][4];
+    dbl4 t1[2][NTJ][2][2];  // [input][column tile][row tile][re, im]
 #pragma unroll
-    for (int mi = 0; mi < NMAT; ++mi) {
-        const int mat = wv + NW * mi;
-        const double* X = (mat >> 1) ? Xw : Xs;
-        const bool sn = mat & 1;
+    for (int inp = 0; inp < 2; ++inp) {
+        const double* X = inp ? Xw : Xs;
 #pragma unroll
-        for (int tile = 0; tile < 4; ++tile) {
-            const int ti = tile >> 1, tj = tile & 1;
-            dbl4 c = {0.0, 0.0, 0.0, 0.0};
+        for (int cj = 0; cj < NTJ; ++cj) {
+            const int tj = tj0 + cj;
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const int row = ti * 16 + li, col = kk * 4 + lk;
-                const int p = (row * col) & 31;
-                const double av = sn ? -S.tws[p] : S.twc[p];
-                const double bv = X[(kk * 4 + lk) * kLd + tj * 16 + li];
-                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+            for (int ti = 0; ti < 2; ++ti) {
+                dbl4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                    const double av = X[(ti * 16 + li) * kLd + kk * 4 + lk];
+                    const int p = ((kk * 4 + lk) * (tj * 16 + li)) & 31;
+                    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av, S.twc[p], cr, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av, -S.tws[p], ci, 0, 0, 0);
+                }
+                t1[inp][cj][ti][0] = cr;
+                t1[inp][cj][ti][1] = ci;
             }
-            acc[mi][tile] = c;
         }
     }
-#pragma unroll
-    for (int mi = 0; mi < NMAT; ++mi) {
-        double* T = S.buf + kTOff + (wv + NW * mi) * (M * kLd);
-#pragma unroll
-        for (int tile = 0; tile < 4; ++tile) {
-            const int ti = tile >> 1, tj = tile & 1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) T[(ti * 16 + lk + 4 * r) * kLd + tj * 16 + li] = acc[mi][tile][r];
-        }
-    }
-    __syncthreads();
+    __syncthreads();  // X is dead; the weight spectrum takes its place
 
-    // ---- stage 2: R = T F --------------------------------------------------
-    // output 0: R_re = T0 C + T1 sin, 1: R_im = T1 C - T0 sin, 2 and 3: the
-    // same for the weights with T2, T3
+    // ---- stage 2: F T for the wave's tiles ----------------------------------
+    // (F T)_re = C T_re + S T_im,  (F T)_im = C T_im - S T_re
+    double* Wd = S.buf;  // weight spectrum, rows duplicated: [64][32] complex
+    double rr[EPT], ri[EPT];
 #pragma unroll
-    for (int mi = 0; mi < NMAT; ++mi) {
-        const int mat = wv + NW * mi;
-        const double* A1 = S.buf + kTOff + ((mat >> 1) * 2) * (M * kLd);
-        const double* A2 = A1 + M * kLd;
-        const bool odd = mat & 1;
+    for (int inp = 1; inp >= 0; --inp) {
 #pragma unroll
-        for (int tile = 0; tile < 4; ++tile) {
-            const int ti = tile >> 1, tj = tile & 1;
-            dbl4 c = {0.0, 0.0, 0.0, 0.0};
+        for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const int row = kk * 4 + lk, col = tj * 16 + li;
-                const int p = (row * col) & 31;
-                const double a1 = A1[(ti * 16 + li) * kLd + kk * 4 + lk];
-                const double a2 = A2[(ti * 16 + li) * kLd + kk * 4 + lk];
-                const double b1 = odd ? -S.tws[p] : S.twc[p];
-                const double b2 = odd ? S.twc[p] : S.tws[p];
-                c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, c, 0, 0, 0);
-            }
-            acc[mi][tile] = c;
-        }
-    }
-    __syncthreads();  // T no longer read
-    double* Wd = S.buf;         // weight spectrum, rows duplicated: [64][32] complex
-    double* Rl = S.buf + 4096;  // residual spectrum [32][32] complex
+            for (int cj = 0; cj < NTJ; ++cj) {
+                const int ti_o = ti0 + ci_, tj = tj0 + cj;
+                dbl4 ore = {0.0, 0.0, 0.0, 0.0}, oim = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int mi = 0; mi < NMAT; ++mi) {
-        const int mat = wv + NW * mi;
-        const int part = mat & 1;  // 0 = real, 1 = imaginary
+                for (int kk = 0; kk < 8; ++kk) {
+                    const int p = ((ti_o * 16 + li) * (kk * 4 + lk)) & 31;
+                    const double c = S.twc[p], sn = S.tws[p];
+                    const double bre = t1[inp][cj][kk >> 2][0][kk & 3];
+                    const double bim = t1[inp][cj][kk >> 2][1][kk & 3];
+                    ore = __builtin_amdgcn_mfma_f64_16x16x4f64(c, bre, ore, 0, 0, 0);
+                    ore = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, bim, ore, 0, 0, 0);
+                    oim = __builtin_amdgcn_mfma_f64_16x16x4f64(c, bim, oim, 0, 0, 0);
+                    oim = __builtin_amdgcn_mfma_f64_16x16x4f64(-sn, bre, oim, 0, 0, 0);
+                }
 #pragma unroll
-        for (int tile = 0; tile < 4; ++tile) {
-            const int ti = tile >> 1, tj = tile & 1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int k = ti * 16 + lk + 4 * r, l = tj * 16 + li;
-                const double v = acc[mi][tile][r];
-                if (mat < 2) {
-                    Rl[(k * 32 + l) * 2 + part] = v;
-                } else {
-                    Wd[(k * 32 + l) * 2 + part] = v;
-                    Wd[((k + 32) * 32 + l) * 2 + part] = v;
+                for (int r = 0; r < 4; ++r) {
+                    const int k = ti_o * 16 + lk + 4 * r, l = tj * 16 + li;
+                    if (inp == 1) {
+                        Wd[(k * 32 + l) * 2] = ore[r];
+                        Wd[(k * 32 + l) * 2 + 1] = oim[r];
+                        Wd[((k + 32) * 32 + l) * 2] = ore[r];
+                        Wd[((k + 32) * 32 + l) * 2 + 1] = oim[r];
+                    } else {
+                        // element order within a lane = increasing spectrum index
+                        const int e = (ci_ * 4 + r) * NTJ + cj;
+                        rr[e] = ore[r];
+                        ri[e] = oim[r];
+                    }
                 }
             }
         }
@@ -271,19 +261,21 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     __syncthreads();
 
     // ---- K greedy steps ----------------------------------------------------
-    // thread t holds spectrum elements t + NT j (row k0 + RS j, column l)
-    const int k0 = t >> 5, l = t & 31;
-    double rr[EPT], ri[EPT];
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        rr[j] = Rl[((k0 + RS * j) * 32 + l) * 2];
-        ri[j] = Rl[((k0 + RS * j) * 32 + l) * 2 + 1];
-    }
+    // lane element e = (row tile ci_, r, column tile cj): k = (ti0+ci_)*16 +
+    // lk + 4r, l = (tj0+cj)*16 + li, index k*32 + l increasing with e
     const bool live = W0 > 0.0;
     const double g = live ? a.gamma / W0 : 0.0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
+    int c_idx[NSLOT];
+    double c_ar[NSLOT], c_ai[NSLOT];
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) {
+        c_idx[q] = 0;
+        c_ar[q] = 0.0;
+        c_ai[q] = 0.0;
+    }
     for (int it = 0; it < K && live; ++it) {
-        // local maximiser: strict '>' over increasing j keeps the first index
+        // local maximiser: strict '>' over increasing index keeps the first
         double lm = rr[0] * rr[0] + ri[0] * ri[0];
         int jl = 0;
 #pragma unroll
@@ -294,15 +286,17 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
             jl = take ? j : jl;
         }
         const double wm = wave_max_nonneg(lm);
-        // the wave's first maximiser in index order (index = t + NT j)
         const uint64_t hit = __ballot(lm == wm);
+        // spectrum index of this lane's local maximiser
+        const int jr = (jl / NTJ) & 3, jci = jl / (4 * NTJ), jcj = jl % NTJ;
+        const int my_idx = ((ti0 + jci) * 16 + lk + 4 * jr) * 32 + (tj0 + jcj) * 16 + li;
         int wl = __ffsll((unsigned long long)hit) - 1;
         if (__popcll(hit) > 1) {
-            // exact tie between lanes: smallest index among them
-            const int cand = (lm == wm) ? (jl * 64 + lane) : 0x7fffffff;
-            int best = cand;
+            // exact tie between lanes: the smallest spectrum index among them
+            int best = (lm == wm) ? my_idx : 0x7fffffff;
             for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
-            wl = best & 63;
+            const uint64_t h2 = __ballot((lm == wm) & (my_idx == best));
+            wl = __ffsll((unsigned long long)h2) - 1;
         }
         const int p = it & 1;
         if (lane == wl) {
@@ -312,7 +306,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 vr = (jl == j) ? rr[j] : vr;
                 vi = (jl == j) ? ri[j] : vi;
             }
-            S.sl[p][wv] = make_double4(wm, vr, vi, (double)(t + NT * jl));
+            S.sl[p][wv] = make_double4(wm, vr, vi, (double)my_idx);
         }
         __syncthreads();  // slot visible to every lane (a single wave keeps LDS order)
         double4 c[NW];
@@ -330,23 +324,47 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         const int IDX = (int)fi;
         const double ar = g * Rr;
         const double ai = g * Ri;
-        if (t == 0) {
-            S.cidx[it] = IDX;
-            S.car[it] = ar;
-            S.cai[it] = ai;
-            if (trace) trace[it] = IDX;
-        }
-        const int u = IDX >> 5, v = IDX & 31;
-        const double* wrow = Wd + (((k0 - u + 32) * 32 + ((l - v) & 31)) * 2);
+        // coefficient of step it is kept by thread it % NT in slot it / NT
+        const bool mine = t == (it % NT);
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const double wr = wrow[j * RS * 32 * 2];
-            const double wi = wrow[j * RS * 32 * 2 + 1];
-            rr[j] = fma(-ar, wr, fma(ai, wi, rr[j]));
-            ri[j] = fma(-ar, wi, fma(-ai, wr, ri[j]));
+        for (int q = 0; q < NSLOT; ++q) {
+            const bool sel = mine & ((it / NT) == q);
+            c_idx[q] = sel ? IDX : c_idx[q];
+            c_ar[q] = sel ? ar : c_ar[q];
+            c_ai[q] = sel ? ai : c_ai[q];
+        }
+        if (trace && t == 0) trace[it] = IDX;
+        const int u = IDX >> 5, v = IDX & 31;
+#pragma unroll
+        for (int ci_ = 0; ci_ < NTI; ++ci_) {
+#pragma unroll
+            for (int cj = 0; cj < NTJ; ++cj) {
+                const double* wrow = Wd + ((((ti0 + ci_) * 16 + lk - u + 32) * 32 + (((tj0 + cj) * 16 + li - v) & 31)) * 2);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = (ci_ * 4 + r) * NTJ + cj;
+                    const double wr = wrow[r * 4 * 32 * 2];
+                    const double wi = wrow[r * 4 * 32 * 2 + 1];
+                    rr[e] = fma(-ar, wr, fma(ai, wi, rr[e]));
+                    ri[e] = fma(-ar, wi, fma(-ai, wr, ri[e]));
+                }
+            }
         }
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
+    __syncthreads();  // the weight spectrum is dead: the coefficient list takes its place
+    double* car = S.buf;
+    double* cai = S.buf + kMaxK;
+    int* cidx = reinterpret_cast<int*>(S.buf + 2 * kMaxK);
+#pragma unroll
+    for (int q = 0; q < NSLOT; ++q) {
+        const int it = q * NT + t;
+        if (it < K) {
+            cidx[it] = c_idx[q];
+            car[it] = c_ar[q];
+            cai[it] = c_ai[q];
+        }
+    }
     __syncthreads();
 
     // ---- synthesis at the block's lost pixels ------------------------------
@@ -360,10 +378,10 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         double val = 0.0;
         if (live) {
             for (int it = sub; it < K; it += gs) {
-                const int idx = S.cidx[it];
+                const int idx = cidx[it];
                 const int u = idx >> 5, v = idx & 31;
                 const int ph = (u * m + v * n) & 31;
-                val += S.car[it] * S.twc[ph] - S.cai[it] * S.tws[ph];
+                val += car[it] * S.twc[ph] - cai[it] * S.tws[ph];
             }
         }
         for (int off = gs >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
@@ -383,6 +401,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     // make this wave's pixel stores visible device-wide before the block is
     // published (the completion flag is set by one thread after a barrier)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();  // the coefficient list is read before the next block reuses the area
 }
 
 // ---------------------------------------------------------------------------
@@ -440,7 +459,7 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
 // persistent and workgroups draw tickets until none is left
 // ---------------------------------------------------------------------------
 template <int NW>
-__global__ void __launch_bounds__(64 * NW) k_fse_blocks(LaunchArgs a, int ticket_base) {
+__global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Shared32& S = *reinterpret_cast<Shared32*>(smem_raw);
     const int t = threadIdx.x;

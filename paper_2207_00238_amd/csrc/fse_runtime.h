@@ -27,6 +27,8 @@ struct Workspace {
     std::vector<double> tab_key;  // parameters the uploaded tables were built for
     uint8_t* host_mask = nullptr;  // pinned staging for mask read-back
     size_t host_mask_cap = 0;
+    uint8_t* stage = nullptr;  // pinned staging for the planning tables
+    size_t stage_cap = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the block kernel(s) of the last call
     bool timed = false;

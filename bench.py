@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--tiles", type=str, default="64",
                     help="comma-separated tile counts for the tile-framework comparison ('' = none)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="length of the served Poisson stream (0 = skip)")
+    ap.add_argument("--no-precision-sweep", action="store_true", help="skip the FP32 / BF16x3 comparison")
     ap.add_argument("--serve-rate", type=float, default=16.0, help="requests per second of the served stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy (a known-size kernel for HBM counter scaling)")
@@ -230,6 +231,9 @@ def main():
                                     "blocks_executed": s["n_blocks"],
                                     "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole})
 
+    if not args.no_precision_sweep:
+        result["precision_sweep"] = precision_sweep(fse, torch, np, img, msk, common, wl, K)
+
     if args.serve_seconds > 0:
         result["served"] = serve_stream(fse, torch, np, imgs, msks, params, args.serve_rate, args.serve_seconds,
                                         nb1, res_single)
@@ -250,6 +254,50 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def precision_sweep(fse, torch, np, img, msk, common, wl, K):
+    """FP32 and BF16x3 against the FP64 path on the first request: speed,
+    pixel error, PSNR change and the rate of blocks whose basis selections
+    leave the FP64 sequence (mirror choices of exactly tied pairs, which give
+    the same real output, are not counted)."""
+    M = 32
+    m = torch.from_numpy(wl.mask).bool()
+    gt = torch.from_numpy(wl.image).double()
+
+    def psnr(x):
+        e = (x.double().clamp(0, 255) - gt)[m]
+        return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
+
+    def run(prec):
+        st0 = fse.fse_params_default(precision=prec, **common)
+        out = torch.empty_like(img)
+        fse.fse_extrapolate(img, msk, st0, out)
+        nb = fse.fse_last_stats()["n_blocks"]
+        sel = torch.full((nb, K), -1, dtype=torch.int32, device=img.device)
+        st0.trace_sel = sel.data_ptr()
+        st0.trace_stride = K
+        st0.trace_capacity = nb
+        t0 = time.perf_counter()
+        fse.fse_extrapolate(img, msk, st0, out)
+        s = fse.fse_last_stats()
+        dt = time.perf_counter() - t0
+        return out.cpu(), sel.cpu().numpy(), nb / dt, s["kernel_ms"]
+
+    ref, sref, v64, k64 = run(0)
+    p64 = psnr(ref)
+    u, v = np.divmod(sref, M)
+    mirror = ((-u) % M) * M + ((-v) % M)
+    res = {"fp64": {"value": v64, "kernel_ms": k64}}
+    for name, prec in (("fp32", 1), ("bf16x3", 2)):
+        out, sel, val, km = run(prec)
+        d = (out.double() - ref.double()).abs()[m]
+        same = (sel == sref) | (sel == mirror)
+        bad = (~same).any(axis=1)
+        res[name] = {"value": val, "kernel_ms": km, "max_abs_dpixel": float(d.max()),
+                     "frac_le_half": float((d <= 0.5).double().mean()), "dpsnr_db": psnr(out) - p64,
+                     "selection_divergence_rate": float(bad.mean())}
+    return res
 
 
 def serve_stream(fse, torch, np, imgs, msks, params, rate, seconds, blocks_per_req, ref0):

@@ -108,7 +108,8 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
     if (!(p->rho > 0.0 && p->rho <= 1.0)) return FSE_ERR_INVALID_ARG;
     if (!(p->gamma > 0.0 && p->gamma < 2.0)) return FSE_ERR_INVALID_ARG;
     if (!(p->recon_weight > 0.0 && p->recon_weight <= 1.0)) return FSE_ERR_INVALID_ARG;
-    if (p->precision != FSE_PREC_F64) return FSE_ERR_UNSUPPORTED;
+    if (p->precision != FSE_PREC_F64 && p->precision != FSE_PREC_F32 && p->precision != FSE_PREC_BF16X3)
+        return FSE_ERR_INVALID_ARG;
     if (p->schedule < FSE_SCHED_PERSISTENT || p->schedule > FSE_SCHED_PER_BLOCK) return FSE_ERR_INVALID_ARG;
     if (p->tiling != FSE_WHOLE && p->tiling != FSE_TILED) return FSE_ERR_INVALID_ARG;
     cls.clear();
@@ -442,15 +443,15 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
             if (grid <= 0) {
                 const int64_t par = (ntk + std::max(1, nkeys) - 1) / std::max(1, nkeys);
                 const int64_t want = std::max<int64_t>(64, ((2 * par + 63) / 64) * 64);
-                grid = (int)std::min<int64_t>(want, persistent_grid(nw));
+                grid = (int)std::min<int64_t>(want, persistent_grid(nw, p->precision));
             }
             grid = (int)std::min<int64_t>(grid, ntk);
-            e = launch_blocks_at(a, nw, grid, 0, st);
+            e = launch_blocks_at(a, nw, p->precision, grid, 0, st);
         } else if (p->schedule == FSE_SCHED_WAVEFRONT) {
             a.counter = nullptr;
             for (int k = 0; k <= max_key && e == hipSuccess; ++k) {
                 const int cnt = kstart[k + 1] - kstart[k];
-                if (cnt > 0) e = launch_blocks_at(a, nw, cnt, kstart[k], st);
+                if (cnt > 0) e = launch_blocks_at(a, nw, p->precision, cnt, kstart[k], st);
             }
         } else {
             // plain path: one launch per block, raster order of each job
@@ -465,7 +466,7 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
                 }
             std::memcpy(ws.stage + o_tk, raster.data(), (size_t)ntk * 8);
             if ((e = up(ws.tickets, ws.stage + o_tk, (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
-            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, 1, (int)k, st);
+            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, p->precision, 1, (int)k, st);
         }
         if (e != hipSuccess) return from_hip(e);
     }

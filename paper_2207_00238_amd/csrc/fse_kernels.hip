@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fse_internal.h"
 #include "fse_runtime.h"
@@ -129,18 +130,79 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 
 
 // ---------------------------------------------------------------------------
-// one M = 32 block, FP64 end to end, NW wave64 per block
+// precision policies
+//   kPrecF64    : FP64 MFMA DFT, FP64 selection loop (the parity path)
+//   kPrecF32    : FP32 MFMA DFT, FP32 loop
+//   kPrecBF16x3 : DFT with BF16 hi/lo splits of both operands, three BF16
+//                 MFMAs per product (hi*hi + hi*lo + lo*hi), FP32 accumulate;
+//                 FP32 loop
+// W0, the coefficients alpha, the synthesis and the reconstructed values stay
+// FP64 in every policy.
+// ---------------------------------------------------------------------------
+constexpr int kPrecF64 = 0, kPrecF32 = 1, kPrecBF16x3 = 2;
+template <int PREC> struct PrecType { using T = float; };
+template <> struct PrecType<kPrecF64> { using T = double; };
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short bf16_bits(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+// x ~ hi + lo with both in bfloat16
+__device__ __forceinline__ void bf16_split(float x, short& hi, short& lo) {
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+}
+
+// one accumulating product step of the DFT for each policy; a and b are the
+// operands of this lane (the BF16 policy passes four consecutive k values)
+__device__ __forceinline__ dbl4 mfma_step(double a, double b, dbl4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma_step(float a, float b, flt4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma_step3(const float (&a)[4], const float (&b)[4], flt4 c) {
+    bf4 ah, al, bh, bl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        short h, l;
+        bf16_split(a[q], h, l);
+        ah[q] = h;
+        al[q] = l;
+        bf16_split(b[q], h, l);
+        bh[q] = h;
+        bl[q] = l;
+    }
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// one M = 32 block, NW wave64 per block, arithmetic policy PREC
 //
 // DFT dataflow: stage 1 forms T = X F (A operand X from LDS, B operand the
 // twiddles), stage 2 forms F T with the B operand taken straight from the
-// stage-1 accumulators: the FP64 MFMA output layout (row 4r + lane/16, column
-// lane%16) is the B-operand layout of the next product's k-step.  Each wave
-// owns NTI x NTJ output tiles of 16 x 16; it computes the stage-1 columns it
-// needs for both inputs (w*s and w), keeps its tiles of R in registers for
-// the K steps and writes its tiles of the weight spectrum to LDS.
+// stage-1 accumulators, which already hold T in the lane layout of the B
+// operand once the contraction index of stage 2 is ordered to match (FP64
+// output rows are lane/16 + 4r; FP32 and BF16 output rows are 4(lane/16) + r).
+// Each wave owns NTI x NTJ output tiles of 16 x 16; it computes the stage-1
+// columns it needs for both inputs (w*s and w), keeps its tiles of R in
+// registers for the K steps and writes its tiles of the weight spectrum to
+// LDS.
 // ---------------------------------------------------------------------------
-template <int NW>
+template <int NW, int PREC>
 __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
+    using T = typename PrecType<PREC>::T;
+    using acc4 = typename std::conditional<PREC == kPrecF64, dbl4, flt4>::type;
+    constexpr bool F64 = PREC == kPrecF64;
     constexpr int NT = 64 * NW;                // threads
     constexpr int NTJ = (NW == 1) ? 2 : 1;     // column tiles per wave
     constexpr int NTI = (NW == 4) ? 1 : 2;     // row tiles per wave
@@ -160,8 +222,8 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
 
     // ---- stage the window: weights and weighted values --------------------
-    double* Xs = S.buf;         // w * s, [m][n] stride kLd
-    double* Xw = Xs + M * kLd;  // w
+    T* Xs = reinterpret_cast<T*>(S.buf);  // w * s, [m][n] stride kLd
+    T* Xw = Xs + M * kLd;                 // w
     double wsum = 0.0;
 #pragma unroll
     for (int j = 0; j < NPIX; ++j) {
@@ -179,8 +241,8 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 v = J.recon[q];
             }
         }
-        Xs[m * kLd + n] = w * v;
-        Xw[m * kLd + n] = w;
+        Xs[m * kLd + n] = (T)(w * v);
+        Xw[m * kLd + n] = (T)w;
         wsum += w;
     }
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
@@ -193,22 +255,39 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     // ---- stage 1: T(:, tj) = X F(:, tj), both inputs ------------------------
     // F = C - i S with C[k,m] = cos(2 pi k m / M), S[k,m] = sin(2 pi k m / M)
     const int li = lane & 15, lk = lane >> 4;
-    dbl4 t1[2][NTJ][2][2];  // [input][column tile][row tile][re, im]
+    acc4 t1[2][NTJ][2][2];  // [input][column tile][row tile][re, im]
 #pragma unroll
     for (int inp = 0; inp < 2; ++inp) {
-        const double* X = inp ? Xw : Xs;
+        const T* X = inp ? Xw : Xs;
 #pragma unroll
         for (int cj = 0; cj < NTJ; ++cj) {
             const int tj = tj0 + cj;
 #pragma unroll
             for (int ti = 0; ti < 2; ++ti) {
-                dbl4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+                acc4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                if constexpr (PREC == kPrecBF16x3) {
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
-                    const double av = X[(ti * 16 + li) * kLd + kk * 4 + lk];
-                    const int p = ((kk * 4 + lk) * (tj * 16 + li)) & 31;
-                    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av, S.twc[p], cr, 0, 0, 0);
-                    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av, -S.tws[p], ci, 0, 0, 0);
+                    for (int kk = 0; kk < 2; ++kk) {
+                        float av[4], bc[4], bs[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = kk * 16 + 4 * lk + q;
+                            av[q] = X[(ti * 16 + li) * kLd + k];
+                            const int p = (k * (tj * 16 + li)) & 31;
+                            bc[q] = (float)S.twc[p];
+                            bs[q] = -(float)S.tws[p];
+                        }
+                        cr = mfma_step3(av, bc, cr);
+                        ci = mfma_step3(av, bs, ci);
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk) {
+                        const T av = X[(ti * 16 + li) * kLd + kk * 4 + lk];
+                        const int p = ((kk * 4 + lk) * (tj * 16 + li)) & 31;
+                        cr = mfma_step(av, (T)S.twc[p], cr);
+                        ci = mfma_step(av, (T)(-S.tws[p]), ci);
+                    }
                 }
                 t1[inp][cj][ti][0] = cr;
                 t1[inp][cj][ti][1] = ci;
@@ -219,8 +298,8 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
 
     // ---- stage 2: F T for the wave's tiles ----------------------------------
     // (F T)_re = C T_re + S T_im,  (F T)_im = C T_im - S T_re
-    double* Wd = S.buf;  // weight spectrum, rows duplicated: [64][32] complex
-    double rr[EPT], ri[EPT];
+    T* Wd = reinterpret_cast<T*>(S.buf);  // weight spectrum, rows duplicated: [64][32] complex
+    T rr[EPT], ri[EPT];
 #pragma unroll
     for (int inp = 1; inp >= 0; --inp) {
 #pragma unroll
@@ -228,21 +307,44 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
 #pragma unroll
             for (int cj = 0; cj < NTJ; ++cj) {
                 const int ti_o = ti0 + ci_, tj = tj0 + cj;
-                dbl4 ore = {0.0, 0.0, 0.0, 0.0}, oim = {0.0, 0.0, 0.0, 0.0};
+                acc4 ore = {0, 0, 0, 0}, oim = {0, 0, 0, 0};
+                if constexpr (PREC == kPrecBF16x3) {
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
-                    const int p = ((ti_o * 16 + li) * (kk * 4 + lk)) & 31;
-                    const double c = S.twc[p], sn = S.tws[p];
-                    const double bre = t1[inp][cj][kk >> 2][0][kk & 3];
-                    const double bim = t1[inp][cj][kk >> 2][1][kk & 3];
-                    ore = __builtin_amdgcn_mfma_f64_16x16x4f64(c, bre, ore, 0, 0, 0);
-                    ore = __builtin_amdgcn_mfma_f64_16x16x4f64(sn, bim, ore, 0, 0, 0);
-                    oim = __builtin_amdgcn_mfma_f64_16x16x4f64(c, bim, oim, 0, 0, 0);
-                    oim = __builtin_amdgcn_mfma_f64_16x16x4f64(-sn, bre, oim, 0, 0, 0);
+                    for (int kk = 0; kk < 2; ++kk) {
+                        float c[4], sn[4], nsn[4], bre[4], bim[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = kk * 16 + 4 * lk + q;
+                            const int p = ((ti_o * 16 + li) * k) & 31;
+                            c[q] = (float)S.twc[p];
+                            sn[q] = (float)S.tws[p];
+                            nsn[q] = -sn[q];
+                            bre[q] = t1[inp][cj][kk][0][q];
+                            bim[q] = t1[inp][cj][kk][1][q];
+                        }
+                        ore = mfma_step3(c, bre, ore);
+                        ore = mfma_step3(sn, bim, ore);
+                        oim = mfma_step3(c, bim, oim);
+                        oim = mfma_step3(nsn, bre, oim);
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk) {
+                        // contraction index held by this lane in accumulator kk
+                        const int k = F64 ? (kk * 4 + lk) : ((kk >> 2) * 16 + 4 * lk + (kk & 3));
+                        const int p = ((ti_o * 16 + li) * k) & 31;
+                        const T c = (T)S.twc[p], sn = (T)S.tws[p];
+                        const T bre = t1[inp][cj][kk >> 2][0][kk & 3];
+                        const T bim = t1[inp][cj][kk >> 2][1][kk & 3];
+                        ore = mfma_step(c, bre, ore);
+                        ore = mfma_step(sn, bim, ore);
+                        oim = mfma_step(c, bim, oim);
+                        oim = mfma_step((T)(-sn), bre, oim);
+                    }
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int k = ti_o * 16 + lk + 4 * r, l = tj * 16 + li;
+                    const int k = ti_o * 16 + (F64 ? (lk + 4 * r) : (4 * lk + r)), l = tj * 16 + li;
                     if (inp == 1) {
                         Wd[(k * 32 + l) * 2] = ore[r];
                         Wd[(k * 32 + l) * 2 + 1] = oim[r];
@@ -261,8 +363,11 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     __syncthreads();
 
     // ---- K greedy steps ----------------------------------------------------
-    // lane element e = (row tile ci_, r, column tile cj): k = (ti0+ci_)*16 +
-    // lk + 4r, l = (tj0+cj)*16 + li, index k*32 + l increasing with e
+    // lane element e = (row tile ci_, r, column tile cj); its row is
+    // (ti0+ci_)*16 + lk + 4r (FP64) or (ti0+ci_)*16 + 4 lk + r (FP32, BF16),
+    // column (tj0+cj)*16 + li; the index k*32 + l increases with e
+    constexpr int ROWK = F64 ? 1 : 4;  // row step per lk
+    constexpr int ROWR = F64 ? 4 : 1;  // row step per r
     const bool live = W0 > 0.0;
     const double g = live ? a.gamma / W0 : 0.0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
@@ -276,20 +381,24 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     }
     for (int it = 0; it < K && live; ++it) {
         // local maximiser: strict '>' over increasing index keeps the first
-        double lm = rr[0] * rr[0] + ri[0] * ri[0];
+        T lm = rr[0] * rr[0] + ri[0] * ri[0];
         int jl = 0;
 #pragma unroll
         for (int j = 1; j < EPT; ++j) {
-            const double e = rr[j] * rr[j] + ri[j] * ri[j];
+            const T e = rr[j] * rr[j] + ri[j] * ri[j];
             const bool take = e > lm;
             lm = take ? e : lm;
             jl = take ? j : jl;
         }
-        const double wm = wave_max_nonneg(lm);
+        T wm;
+        if constexpr (F64)
+            wm = wave_max_nonneg(lm);
+        else
+            wm = __uint_as_float(wave_umax(__float_as_uint(lm)));
         const uint64_t hit = __ballot(lm == wm);
         // spectrum index of this lane's local maximiser
         const int jr = (jl / NTJ) & 3, jci = jl / (4 * NTJ), jcj = jl % NTJ;
-        const int my_idx = ((ti0 + jci) * 16 + lk + 4 * jr) * 32 + (tj0 + jcj) * 16 + li;
+        const int my_idx = ((ti0 + jci) * 16 + ROWK * lk + ROWR * jr) * 32 + (tj0 + jcj) * 16 + li;
         int wl = __ffsll((unsigned long long)hit) - 1;
         if (__popcll(hit) > 1) {
             // exact tie between lanes: the smallest spectrum index among them
@@ -300,13 +409,13 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         }
         const int p = it & 1;
         if (lane == wl) {
-            double vr = rr[0], vi = ri[0];
+            T vr = rr[0], vi = ri[0];
 #pragma unroll
             for (int j = 1; j < EPT; ++j) {
                 vr = (jl == j) ? rr[j] : vr;
                 vi = (jl == j) ? ri[j] : vi;
             }
-            S.sl[p][wv] = make_double4(wm, vr, vi, (double)my_idx);
+            S.sl[p][wv] = make_double4((double)wm, (double)vr, (double)vi, (double)my_idx);
         }
         __syncthreads();  // slot visible to every lane (a single wave keeps LDS order)
         double4 c[NW];
@@ -335,18 +444,20 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         }
         if (trace && t == 0) trace[it] = IDX;
         const int u = IDX >> 5, v = IDX & 31;
+        const T tar = (T)ar, tai = (T)ai;
 #pragma unroll
         for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
             for (int cj = 0; cj < NTJ; ++cj) {
-                const double* wrow = Wd + ((((ti0 + ci_) * 16 + lk - u + 32) * 32 + (((tj0 + cj) * 16 + li - v) & 31)) * 2);
+                const T* wrow =
+                    Wd + ((((ti0 + ci_) * 16 + ROWK * lk - u + 32) * 32 + (((tj0 + cj) * 16 + li - v) & 31)) * 2);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int e = (ci_ * 4 + r) * NTJ + cj;
-                    const double wr = wrow[r * 4 * 32 * 2];
-                    const double wi = wrow[r * 4 * 32 * 2 + 1];
-                    rr[e] = fma(-ar, wr, fma(ai, wi, rr[e]));
-                    ri[e] = fma(-ar, wi, fma(-ai, wr, ri[e]));
+                    const T wr = wrow[r * ROWR * 32 * 2];
+                    const T wi = wrow[r * ROWR * 32 * 2 + 1];
+                    rr[e] = fma(-tar, wr, fma(tai, wi, rr[e]));
+                    ri[e] = fma(-tar, wi, fma(-tai, wr, ri[e]));
                 }
             }
         }
@@ -458,7 +569,7 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
 // block kernel: tickets in dispatch order; with counter != null the grid is
 // persistent and workgroups draw tickets until none is left
 // ---------------------------------------------------------------------------
-template <int NW>
+template <int NW, int PREC>
 __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Shared32& S = *reinterpret_cast<Shared32*>(smem_raw);
@@ -489,7 +600,7 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchA
         if (job < 0) break;
         const JobDev& J = a.jobs[job];
         wait_predecessors<64 * NW>(a, J, blk, S);
-        process_block32<NW>(a, J, blk, S);
+        process_block32<NW, PREC>(a, J, blk, S);
         __syncthreads();
         if (t == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -500,26 +611,21 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchA
     }
 }
 
-template <int NW>
-static const void* kernel_ptr() {
-    return (const void*)k_fse_blocks<NW>;
-}
-
-static const void* kernel_for(int nw) {
-    switch (nw) {
-        case 1: return kernel_ptr<1>();
-        case 2: return kernel_ptr<2>();
-        default: return kernel_ptr<4>();
-    }
+static const void* kernel_for(int nw, int prec) {
+#define FSE_K(N, P) (const void*)k_fse_blocks<N, P>
+    if (prec == kPrecF32) return nw == 1 ? FSE_K(1, 1) : nw == 2 ? FSE_K(2, 1) : FSE_K(4, 1);
+    if (prec == kPrecBF16x3) return nw == 1 ? FSE_K(1, 2) : nw == 2 ? FSE_K(2, 2) : FSE_K(4, 2);
+    return nw == 1 ? FSE_K(1, 0) : nw == 2 ? FSE_K(2, 0) : FSE_K(4, 0);
+#undef FSE_K
 }
 
 size_t shared_bytes_blocks() { return sizeof(Shared32); }
 
-int persistent_grid(int nw) {
+int persistent_grid(int nw, int prec) {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* k = kernel_for(nw);
+    const void* k = kernel_for(nw, prec);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * nw, sizeof(Shared32)) != hipSuccess ||
         per_cu < 1)
@@ -527,20 +633,11 @@ int persistent_grid(int nw) {
     return std::max(1, cus) * per_cu;
 }
 
-hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int grid, int ticket_base, hipStream_t st) {
-    const void* k = kernel_for(nw);
-    static bool attr_set[5] = {false, false, false, false, false};
-    if (!attr_set[nw]) {
-        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
-        attr_set[nw] = true;
-    }
-    if (nw == 1)
-        hipLaunchKernelGGL(k_fse_blocks<1>, dim3(grid), dim3(64), sizeof(Shared32), st, a, ticket_base);
-    else if (nw == 2)
-        hipLaunchKernelGGL(k_fse_blocks<2>, dim3(grid), dim3(128), sizeof(Shared32), st, a, ticket_base);
-    else
-        hipLaunchKernelGGL(k_fse_blocks<4>, dim3(grid), dim3(256), sizeof(Shared32), st, a, ticket_base);
-    return hipGetLastError();
+hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int prec, int grid, int ticket_base, hipStream_t st) {
+    const void* k = kernel_for(nw, prec);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
+    void* args[] = {(void*)&a, (void*)&ticket_base};
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * nw), args, sizeof(Shared32), st);
 }
 
 }  // namespace fse

@@ -117,7 +117,7 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
         const fse_class_t& k = p->classes[c];
         if (k.block < 1 || k.border < 0 || k.iters < 0 || k.iters > 256) return FSE_ERR_INVALID_ARG;
         const int M = k.block + 2 * k.border;
-        if (M != 32) return FSE_ERR_UNSUPPORTED;
+        if (M != 32 && M != 64) return FSE_ERR_UNSUPPORTED;
         if (k.block > 16 || (k.block & (k.block - 1)) != 0) return FSE_ERR_UNSUPPORTED;
         cls.push_back({k.block, k.border, k.iters, M});
     }
@@ -431,7 +431,9 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
         if ((e = hipEventCreate(&ws.ev1)) != hipSuccess) return from_hip(e);
     }
     if ((e = hipEventRecord(ws.ev0, st)) != hipSuccess) return from_hip(e);
-    const int nw = p->block_waves > 0 ? p->block_waves : 4;
+    bool wide = false;
+    for (auto& c : cls) wide |= (c.M == 64);
+    const int nw = wide ? 4 : (p->block_waves > 0 ? p->block_waves : 4);
     if (ntk > 0) {
         if (p->schedule == FSE_SCHED_PERSISTENT) {
             a.counter = counter;
@@ -443,15 +445,15 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
             if (grid <= 0) {
                 const int64_t par = (ntk + std::max(1, nkeys) - 1) / std::max(1, nkeys);
                 const int64_t want = std::max<int64_t>(64, ((2 * par + 63) / 64) * 64);
-                grid = (int)std::min<int64_t>(want, persistent_grid(nw, p->precision));
+                grid = (int)std::min<int64_t>(want, persistent_grid(nw, p->precision, wide));
             }
             grid = (int)std::min<int64_t>(grid, ntk);
-            e = launch_blocks_at(a, nw, p->precision, grid, 0, st);
+            e = launch_blocks_at(a, nw, p->precision, wide, grid, 0, st);
         } else if (p->schedule == FSE_SCHED_WAVEFRONT) {
             a.counter = nullptr;
             for (int k = 0; k <= max_key && e == hipSuccess; ++k) {
                 const int cnt = kstart[k + 1] - kstart[k];
-                if (cnt > 0) e = launch_blocks_at(a, nw, p->precision, cnt, kstart[k], st);
+                if (cnt > 0) e = launch_blocks_at(a, nw, p->precision, wide, cnt, kstart[k], st);
             }
         } else {
             // plain path: one launch per block, raster order of each job
@@ -466,7 +468,7 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
                 }
             std::memcpy(ws.stage + o_tk, raster.data(), (size_t)ntk * 8);
             if ((e = up(ws.tickets, ws.stage + o_tk, (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
-            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, p->precision, 1, (int)k, st);
+            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, p->precision, wide, 1, (int)k, st);
         }
         if (e != hipSuccess) return from_hip(e);
     }

@@ -63,7 +63,8 @@ hipError_t launch_init_job(const JobDev* jobs_dev, int n_jobs, int max_w, int ma
                            int32_t* error, int64_t* degenerate, hipStream_t st);
 // grid workgroups; with a.counter set they draw tickets from the counter,
 // otherwise workgroup g runs ticket ticket_base + g
-hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int prec, int grid, int ticket_base, hipStream_t st);
-size_t shared_bytes_blocks();
+hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int prec, bool wide, int grid, int ticket_base,
+                            hipStream_t st);
+size_t shared_bytes_blocks(bool wide);
 
 }  // namespace fse

@@ -77,21 +77,30 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
     return ay0 < by1 && by0 < ay1 && ax0 < bx1 && bx0 < ax1;
 }
 
-// LDS layout (doubles) for M = 32.  One 32 KB area holds, in turn: the DFT
-// operands X (w*s and w, 32 x 33 each); the weight spectrum with duplicated
-// rows (64 x 32 complex) during the K steps; the coefficient list for the
-// synthesis.
-constexpr int kLd = 33;  // padded row stride of the DFT operands
-constexpr int kBufDoubles = 4096;
+// LDS layout.  One area holds, in turn: the DFT operands X (w*s and w, M x
+// (M+1) each); the weight spectrum during the K steps (M = 32: 64 x 32
+// complex with duplicated rows; M = 64: 64 x 64 complex); the coefficient list
+// for the synthesis.  Sized for M = 32 (32 KB) or, when a launch has M = 64
+// blocks, for M = 64 (65 KB).
 constexpr int kMaxK = 256;
+constexpr int kBufDoubles32 = 4096;
+constexpr int kBufDoubles64 = 2 * 64 * 65;
 
-struct Shared32 {
-    double buf[kBufDoubles];
-    double twc[32], tws[32];
+struct SharedHead {
+    double twc32[32], tws32[32];
+    double twc64[64], tws64[64];
     double part[4];
     double4 sl[2][4];  // per wave: energy, Re R, Im R, index
     int job, blk, wait_fail;
 };
+
+template <int NBUF>
+struct SharedT {
+    SharedHead h;
+    double buf[NBUF];
+};
+using Shared32 = SharedT<kBufDoubles32>;
+using Shared64 = SharedT<kBufDoubles64>;
 
 // Unsigned 32-bit maximum over a wave64 with DPP; the result is valid in
 // lane 63.  Non-negative doubles order like their bit patterns, so the high
@@ -186,7 +195,8 @@ __device__ __forceinline__ flt4 mfma_step3(const float (&a)[4], const float (&b)
 }
 
 // ---------------------------------------------------------------------------
-// one M = 32 block, NW wave64 per block, arithmetic policy PREC
+// one block with an M x M window (M = 32 or 64), NW wave64 per block,
+// arithmetic policy PREC
 //
 // DFT dataflow: stage 1 forms T = X F (A operand X from LDS, B operand the
 // twiddles), stage 2 forms F T with the B operand taken straight from the
@@ -198,36 +208,53 @@ __device__ __forceinline__ flt4 mfma_step3(const float (&a)[4], const float (&b)
 // registers for the K steps and writes its tiles of the weight spectrum to
 // LDS.
 // ---------------------------------------------------------------------------
-template <int NW, int PREC>
-__device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
+template <int M, int NW>
+struct TileMap {
+    static constexpr int TL = M / 16;                                    // tiles per dimension
+    static constexpr int NTJ = (M == 32) ? ((NW == 1) ? 2 : 1) : (4 / NW);  // column tiles per wave
+    static constexpr int NTI = (M == 32) ? ((NW == 4) ? 1 : 2) : 4;       // row tiles per wave
+    __device__ static int ti0(int wv) { return (M == 32 && NW == 4) ? (wv >> 1) : 0; }
+    __device__ static int tj0(int wv) {
+        return (M == 32) ? ((NW == 4) ? (wv & 1) : (NW == 2 ? wv : 0)) : wv * NTJ;
+    }
+};
+
+template <int M, int NW, int PREC>
+__device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& H, double* buf) {
     using T = typename PrecType<PREC>::T;
     using acc4 = typename std::conditional<PREC == kPrecF64, dbl4, flt4>::type;
+    using TM = TileMap<M, NW>;
     constexpr bool F64 = PREC == kPrecF64;
-    constexpr int NT = 64 * NW;                // threads
-    constexpr int NTJ = (NW == 1) ? 2 : 1;     // column tiles per wave
-    constexpr int NTI = (NW == 4) ? 1 : 2;     // row tiles per wave
-    constexpr int EPT = NTI * NTJ * 4;         // spectrum elements per lane
-    constexpr int NPIX = 1024 / NT;            // window pixels per thread while staging
-    constexpr int RS = NT / 32;
+    constexpr int NT = 64 * NW;               // threads
+    constexpr int NTJ = TM::NTJ, NTI = TM::NTI;
+    constexpr int EPT = NTI * NTJ * 4;        // spectrum elements per lane
+    constexpr int NPIX = M * M / NT;          // window pixels per thread while staging
+    constexpr int RS = NT / M;                // window-row step between a thread's pixels
+    constexpr int KK = M / 4;                 // k-steps of a 16x16x4 product
+    constexpr int KB = M / 16;                // k-steps of a 16x16x16 product
+    constexpr int LD = M + 1;                 // padded row stride of X
+    constexpr int MASK = M - 1;
+    constexpr int LOGM = (M == 32) ? 5 : 6;
+    constexpr bool DUP = (M == 32);           // weight spectrum rows duplicated
     constexpr int NSLOT = (kMaxK + NT - 1) / NT;  // coefficient slots per thread
-    constexpr int M = 32;
+    const double* twc = (M == 32) ? H.twc32 : H.twc64;
+    const double* tws = (M == 32) ? H.tws32 : H.tws64;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = t >> 6;
-    const int tj0 = (NW == 4) ? (wv & 1) : (NW == 2 ? wv : 0);
-    const int ti0 = (NW == 4) ? (wv >> 1) : 0;
+    const int ti0 = TM::ti0(wv), tj0 = TM::tj0(wv);
     const int4 d = J.desc[blk];
     const ClassDev& C = a.cls[d.z];
     const int B = C.B, b = C.b, K = C.K;
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
 
     // ---- stage the window: weights and weighted values --------------------
-    T* Xs = reinterpret_cast<T*>(S.buf);  // w * s, [m][n] stride kLd
-    T* Xw = Xs + M * kLd;                 // w
+    T* Xs = reinterpret_cast<T*>(buf);  // w * s, [m][n] stride LD
+    T* Xw = Xs + M * LD;                // w
     double wsum = 0.0;
 #pragma unroll
     for (int j = 0; j < NPIX; ++j) {
-        const int m = (t >> 5) + RS * j, n = t & 31;
+        const int m = (t >> LOGM) + RS * j, n = t & MASK;
         const int y = wy + m, x = wx + n;
         double w = 0.0, v = 0.0;
         if (y >= 0 && y < J.H && x >= 0 && x < J.W) {
@@ -241,21 +268,21 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 v = J.recon[q];
             }
         }
-        Xs[m * kLd + n] = (T)(w * v);
-        Xw[m * kLd + n] = (T)w;
+        Xs[m * LD + n] = (T)(w * v);
+        Xw[m * LD + n] = (T)w;
         wsum += w;
     }
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
-    if (lane == 0) S.part[wv] = wsum;
+    if (lane == 0) H.part[wv] = wsum;
     __syncthreads();
-    double W0 = S.part[0];
+    double W0 = H.part[0];
 #pragma unroll
-    for (int q = 1; q < NW; ++q) W0 += S.part[q];
+    for (int q = 1; q < NW; ++q) W0 += H.part[q];
 
     // ---- stage 1: T(:, tj) = X F(:, tj), both inputs ------------------------
     // F = C - i S with C[k,m] = cos(2 pi k m / M), S[k,m] = sin(2 pi k m / M)
     const int li = lane & 15, lk = lane >> 4;
-    acc4 t1[2][NTJ][2][2];  // [input][column tile][row tile][re, im]
+    acc4 t1[2][NTJ][TM::TL][2];  // [input][column tile][row tile][re, im]
 #pragma unroll
     for (int inp = 0; inp < 2; ++inp) {
         const T* X = inp ? Xw : Xs;
@@ -263,30 +290,30 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         for (int cj = 0; cj < NTJ; ++cj) {
             const int tj = tj0 + cj;
 #pragma unroll
-            for (int ti = 0; ti < 2; ++ti) {
+            for (int ti = 0; ti < TM::TL; ++ti) {
                 acc4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
                 if constexpr (PREC == kPrecBF16x3) {
 #pragma unroll
-                    for (int kk = 0; kk < 2; ++kk) {
+                    for (int kk = 0; kk < KB; ++kk) {
                         float av[4], bc[4], bs[4];
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const int k = kk * 16 + 4 * lk + q;
-                            av[q] = X[(ti * 16 + li) * kLd + k];
-                            const int p = (k * (tj * 16 + li)) & 31;
-                            bc[q] = (float)S.twc[p];
-                            bs[q] = -(float)S.tws[p];
+                            av[q] = X[(ti * 16 + li) * LD + k];
+                            const int p = (k * (tj * 16 + li)) & MASK;
+                            bc[q] = (float)twc[p];
+                            bs[q] = -(float)tws[p];
                         }
                         cr = mfma_step3(av, bc, cr);
                         ci = mfma_step3(av, bs, ci);
                     }
                 } else {
 #pragma unroll
-                    for (int kk = 0; kk < 8; ++kk) {
-                        const T av = X[(ti * 16 + li) * kLd + kk * 4 + lk];
-                        const int p = ((kk * 4 + lk) * (tj * 16 + li)) & 31;
-                        cr = mfma_step(av, (T)S.twc[p], cr);
-                        ci = mfma_step(av, (T)(-S.tws[p]), ci);
+                    for (int kk = 0; kk < KK; ++kk) {
+                        const T av = X[(ti * 16 + li) * LD + kk * 4 + lk];
+                        const int p = ((kk * 4 + lk) * (tj * 16 + li)) & MASK;
+                        cr = mfma_step(av, (T)twc[p], cr);
+                        ci = mfma_step(av, (T)(-tws[p]), ci);
                     }
                 }
                 t1[inp][cj][ti][0] = cr;
@@ -298,7 +325,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
 
     // ---- stage 2: F T for the wave's tiles ----------------------------------
     // (F T)_re = C T_re + S T_im,  (F T)_im = C T_im - S T_re
-    T* Wd = reinterpret_cast<T*>(S.buf);  // weight spectrum, rows duplicated: [64][32] complex
+    T* Wd = reinterpret_cast<T*>(buf);  // weight spectrum [DUP ? 2M : M][M] complex
     T rr[EPT], ri[EPT];
 #pragma unroll
     for (int inp = 1; inp >= 0; --inp) {
@@ -310,14 +337,14 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 acc4 ore = {0, 0, 0, 0}, oim = {0, 0, 0, 0};
                 if constexpr (PREC == kPrecBF16x3) {
 #pragma unroll
-                    for (int kk = 0; kk < 2; ++kk) {
+                    for (int kk = 0; kk < KB; ++kk) {
                         float c[4], sn[4], nsn[4], bre[4], bim[4];
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const int k = kk * 16 + 4 * lk + q;
-                            const int p = ((ti_o * 16 + li) * k) & 31;
-                            c[q] = (float)S.twc[p];
-                            sn[q] = (float)S.tws[p];
+                            const int p = ((ti_o * 16 + li) * k) & MASK;
+                            c[q] = (float)twc[p];
+                            sn[q] = (float)tws[p];
                             nsn[q] = -sn[q];
                             bre[q] = t1[inp][cj][kk][0][q];
                             bim[q] = t1[inp][cj][kk][1][q];
@@ -329,11 +356,11 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                     }
                 } else {
 #pragma unroll
-                    for (int kk = 0; kk < 8; ++kk) {
+                    for (int kk = 0; kk < KK; ++kk) {
                         // contraction index held by this lane in accumulator kk
                         const int k = F64 ? (kk * 4 + lk) : ((kk >> 2) * 16 + 4 * lk + (kk & 3));
-                        const int p = ((ti_o * 16 + li) * k) & 31;
-                        const T c = (T)S.twc[p], sn = (T)S.tws[p];
+                        const int p = ((ti_o * 16 + li) * k) & MASK;
+                        const T c = (T)twc[p], sn = (T)tws[p];
                         const T bre = t1[inp][cj][kk >> 2][0][kk & 3];
                         const T bim = t1[inp][cj][kk >> 2][1][kk & 3];
                         ore = mfma_step(c, bre, ore);
@@ -346,10 +373,12 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 for (int r = 0; r < 4; ++r) {
                     const int k = ti_o * 16 + (F64 ? (lk + 4 * r) : (4 * lk + r)), l = tj * 16 + li;
                     if (inp == 1) {
-                        Wd[(k * 32 + l) * 2] = ore[r];
-                        Wd[(k * 32 + l) * 2 + 1] = oim[r];
-                        Wd[((k + 32) * 32 + l) * 2] = ore[r];
-                        Wd[((k + 32) * 32 + l) * 2 + 1] = oim[r];
+                        Wd[(k * M + l) * 2] = ore[r];
+                        Wd[(k * M + l) * 2 + 1] = oim[r];
+                        if (DUP) {
+                            Wd[((k + M) * M + l) * 2] = ore[r];
+                            Wd[((k + M) * M + l) * 2 + 1] = oim[r];
+                        }
                     } else {
                         // element order within a lane = increasing spectrum index
                         const int e = (ci_ * 4 + r) * NTJ + cj;
@@ -365,7 +394,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     // ---- K greedy steps ----------------------------------------------------
     // lane element e = (row tile ci_, r, column tile cj); its row is
     // (ti0+ci_)*16 + lk + 4r (FP64) or (ti0+ci_)*16 + 4 lk + r (FP32, BF16),
-    // column (tj0+cj)*16 + li; the index k*32 + l increases with e
+    // column (tj0+cj)*16 + li; the index k*M + l increases with e
     constexpr int ROWK = F64 ? 1 : 4;  // row step per lk
     constexpr int ROWR = F64 ? 4 : 1;  // row step per r
     const bool live = W0 > 0.0;
@@ -398,7 +427,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         const uint64_t hit = __ballot(lm == wm);
         // spectrum index of this lane's local maximiser
         const int jr = (jl / NTJ) & 3, jci = jl / (4 * NTJ), jcj = jl % NTJ;
-        const int my_idx = ((ti0 + jci) * 16 + ROWK * lk + ROWR * jr) * 32 + (tj0 + jcj) * 16 + li;
+        const int my_idx = ((ti0 + jci) * 16 + ROWK * lk + ROWR * jr) * M + (tj0 + jcj) * 16 + li;
         int wl = __ffsll((unsigned long long)hit) - 1;
         if (__popcll(hit) > 1) {
             // exact tie between lanes: the smallest spectrum index among them
@@ -415,12 +444,12 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
                 vr = (jl == j) ? rr[j] : vr;
                 vi = (jl == j) ? ri[j] : vi;
             }
-            S.sl[p][wv] = make_double4((double)wm, (double)vr, (double)vi, (double)my_idx);
+            H.sl[p][wv] = make_double4((double)wm, (double)vr, (double)vi, (double)my_idx);
         }
         __syncthreads();  // slot visible to every lane (a single wave keeps LDS order)
         double4 c[NW];
 #pragma unroll
-        for (int q = 0; q < NW; ++q) c[q] = S.sl[p][q];
+        for (int q = 0; q < NW; ++q) c[q] = H.sl[p][q];
         double E = c[0].x, Rr = c[0].y, Ri = c[0].z, fi = c[0].w;
 #pragma unroll
         for (int q = 1; q < NW; ++q) {
@@ -443,19 +472,21 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
             c_ai[q] = sel ? ai : c_ai[q];
         }
         if (trace && t == 0) trace[it] = IDX;
-        const int u = IDX >> 5, v = IDX & 31;
+        const int u = IDX >> LOGM, v = IDX & MASK;
         const T tar = (T)ar, tai = (T)ai;
 #pragma unroll
         for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
             for (int cj = 0; cj < NTJ; ++cj) {
-                const T* wrow =
-                    Wd + ((((ti0 + ci_) * 16 + ROWK * lk - u + 32) * 32 + (((tj0 + cj) * 16 + li - v) & 31)) * 2);
+                const int col = ((tj0 + cj) * 16 + li - v) & MASK;
+                const int row0 = (ti0 + ci_) * 16 + ROWK * lk - u;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int e = (ci_ * 4 + r) * NTJ + cj;
-                    const T wr = wrow[r * ROWR * 32 * 2];
-                    const T wi = wrow[r * ROWR * 32 * 2 + 1];
+                    // DUP: rows row0 + M + ROWR r lie in [1, 2M) of the duplicated table
+                    const T* w = DUP ? (Wd + (((row0 + M) << LOGM) + col) * 2 + r * (ROWR * M * 2))
+                                     : (Wd + ((((row0 + ROWR * r) & MASK) << LOGM) + col) * 2);
+                    const T wr = w[0], wi = w[1];
                     rr[e] = fma(-tar, wr, fma(tai, wi, rr[e]));
                     ri[e] = fma(-tar, wi, fma(-tai, wr, ri[e]));
                 }
@@ -464,9 +495,9 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
     __syncthreads();  // the weight spectrum is dead: the coefficient list takes its place
-    double* car = S.buf;
-    double* cai = S.buf + kMaxK;
-    int* cidx = reinterpret_cast<int*>(S.buf + 2 * kMaxK);
+    double* car = buf;
+    double* cai = buf + kMaxK;
+    int* cidx = reinterpret_cast<int*>(buf + 2 * kMaxK);
 #pragma unroll
     for (int q = 0; q < NSLOT; ++q) {
         const int it = q * NT + t;
@@ -490,9 +521,9 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
         if (live) {
             for (int it = sub; it < K; it += gs) {
                 const int idx = cidx[it];
-                const int u = idx >> 5, v = idx & 31;
-                const int ph = (u * m + v * n) & 31;
-                val += car[it] * S.twc[ph] - cai[it] * S.tws[ph];
+                const int u = idx >> LOGM, v = idx & MASK;
+                const int ph = (u * m + v * n) & MASK;
+                val += car[it] * twc[ph] - cai[it] * tws[ph];
             }
         }
         for (int off = gs >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
@@ -520,7 +551,7 @@ __device__ void process_block32(const LaunchArgs& a, const JobDev& J, int blk, S
 // window, or whose window meets this block's lost pixels
 // ---------------------------------------------------------------------------
 template <int NT>
-__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, Shared32& S) {
+__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S) {
     const int4 d = J.desc[blk];
     const int4 lb = J.lbox[blk];
     const ClassDev& Cj = a.cls[d.z];
@@ -569,14 +600,21 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
 // block kernel: tickets in dispatch order; with counter != null the grid is
 // persistent and workgroups draw tickets until none is left
 // ---------------------------------------------------------------------------
-template <int NW, int PREC>
-__global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
+// WIDE: the launch holds M = 64 blocks (the shared area is sized for them and
+// each block branches on its window size).
+template <int NW, int PREC, bool WIDE>
+__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Shared32& S = *reinterpret_cast<Shared32*>(smem_raw);
+    SharedHead& H = *reinterpret_cast<SharedHead*>(smem_raw);
+    double* buf = reinterpret_cast<double*>(smem_raw + sizeof(SharedHead));
     const int t = threadIdx.x;
     if (t < 32) {
-        S.twc[t] = a.tw32[t];
-        S.tws[t] = a.tw32[32 + t];
+        H.twc32[t] = a.tw32[t];
+        H.tws32[t] = a.tw32[32 + t];
+    }
+    if (t < 64) {
+        H.twc64[t] = a.tw64[t];
+        H.tws64[t] = a.tw64[64 + t];
     }
     for (;;) {
         if (t == 0) {
@@ -587,20 +625,27 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchA
                 tk = ticket_base + blockIdx.x;
             if (tk < a.n_tickets) {
                 const int2 tkt = a.tickets[tk];
-                S.job = tkt.x;
-                S.blk = tkt.y;
+                H.job = tkt.x;
+                H.blk = tkt.y;
             } else {
-                S.job = -1;
-                S.blk = -1;
+                H.job = -1;
+                H.blk = -1;
             }
-            S.wait_fail = 0;
+            H.wait_fail = 0;
         }
         __syncthreads();
-        const int job = S.job, blk = S.blk;
+        const int job = H.job, blk = H.blk;
         if (job < 0) break;
         const JobDev& J = a.jobs[job];
-        wait_predecessors<64 * NW>(a, J, blk, S);
-        process_block32<NW, PREC>(a, J, blk, S);
+        wait_predecessors<64 * NW>(a, J, blk, H);
+        if constexpr (WIDE) {
+            if (a.cls[J.desc[blk].z].M == 64)
+                process_block<64, NW, PREC>(a, J, blk, H, buf);
+            else
+                process_block<32, NW, PREC>(a, J, blk, H, buf);
+        } else {
+            process_block<32, NW, PREC>(a, J, blk, H, buf);
+        }
         __syncthreads();
         if (t == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -611,33 +656,42 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 1) k_fse_blocks(LaunchA
     }
 }
 
-static const void* kernel_for(int nw, int prec) {
-#define FSE_K(N, P) (const void*)k_fse_blocks<N, P>
+static const void* kernel_for(int nw, int prec, bool wide) {
+    if (wide) {  // M = 64 blocks run with four waves
+        if (prec == kPrecF32) return (const void*)k_fse_blocks<4, 1, true>;
+        if (prec == kPrecBF16x3) return (const void*)k_fse_blocks<4, 2, true>;
+        return (const void*)k_fse_blocks<4, 0, true>;
+    }
+#define FSE_K(N, P) (const void*)k_fse_blocks<N, P, false>
     if (prec == kPrecF32) return nw == 1 ? FSE_K(1, 1) : nw == 2 ? FSE_K(2, 1) : FSE_K(4, 1);
     if (prec == kPrecBF16x3) return nw == 1 ? FSE_K(1, 2) : nw == 2 ? FSE_K(2, 2) : FSE_K(4, 2);
     return nw == 1 ? FSE_K(1, 0) : nw == 2 ? FSE_K(2, 0) : FSE_K(4, 0);
 #undef FSE_K
 }
 
-size_t shared_bytes_blocks() { return sizeof(Shared32); }
+size_t shared_bytes_blocks(bool wide) { return wide ? sizeof(Shared64) : sizeof(Shared32); }
 
-int persistent_grid(int nw, int prec) {
+int persistent_grid(int nw, int prec, bool wide) {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* k = kernel_for(nw, prec);
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * nw, sizeof(Shared32)) != hipSuccess ||
-        per_cu < 1)
+    const void* k = kernel_for(nw, prec, wide);
+    const int nthreads = 64 * (wide ? 4 : nw);
+    const int lds = (int)shared_bytes_blocks(wide);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nthreads, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     return std::max(1, cus) * per_cu;
 }
 
-hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int prec, int grid, int ticket_base, hipStream_t st) {
-    const void* k = kernel_for(nw, prec);
-    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Shared32));
+hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int prec, bool wide, int grid, int ticket_base,
+                            hipStream_t st) {
+    const void* k = kernel_for(nw, prec, wide);
+    const int nthreads = 64 * (wide ? 4 : nw);
+    const int lds = (int)shared_bytes_blocks(wide);
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     void* args[] = {(void*)&a, (void*)&ticket_base};
-    return hipLaunchKernel(k, dim3(grid), dim3(64 * nw), args, sizeof(Shared32), st);
+    return hipLaunchKernel(k, dim3(grid), dim3(nthreads), args, lds, st);
 }
 
 }  // namespace fse

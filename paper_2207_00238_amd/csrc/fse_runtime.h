@@ -45,6 +45,6 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
 void fse_last_stats_nowait(fse_run_stats_t* st);
 Workspace* workspace_for(hipStream_t st);
 void release_all_workspaces();
-int persistent_grid(int nw, int prec);  // resident workgroups of the block kernel on the current device
+int persistent_grid(int nw, int prec, bool wide);  // resident workgroups of the block kernel on the current device
 
 }  // namespace fse

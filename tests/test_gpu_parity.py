@@ -196,3 +196,27 @@ def test_batch_of_images_matches_each_oracle():
 def test_block_wave_variants(nw):
     wl = synth.workload("small")
     _check(wl.image, wl.mask, wl.classes, block_waves=nw)
+
+
+@pytest.mark.parametrize("precision", [0])
+def test_mixed_block_classes_64_windows(precision):
+    # 16x16 and 8x8 losses with 64x64 windows, row defects with 4x4 blocks
+    W, H = 200, 168
+    img = synth.synth_image(W, H, seed=91, period_max=128.0)
+    mask = synth.mask_mixed(W, H, seed=92, frac8=0.10, frac16=0.05, row_fraction=0.02)
+    cls = ((16, 24, 40), (8, 28, 40), (4, 14, 30))
+    ref = O.image(img, mask, cls)
+    got, _, st = _run(img, mask, cls, precision=precision)
+    m = mask.astype(bool)
+    y, x, c, _ = O.plan(mask, cls)
+    assert st["n_blocks"] == len(y) and (c == 0).any() and (c == 1).any() and (c == 2).any()
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got - ref)[m].max() <= TIGHT
+
+
+def test_single_class_64_window():
+    # one class with a 64x64 window: B = 8, b = 28
+    img = synth.synth_image(128, 96, seed=93)
+    mask = synth.mask_blocks(128, 96, 8, 0.15, seed=94)
+    cls = ((8, 28, 60),)
+    _check(img, mask, cls)

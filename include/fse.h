@@ -174,6 +174,21 @@ fse_status_t fse_last_stats(fse_run_stats_t* st);
 /* Free all cached device workspace (waits for the streams that use it). */
 fse_status_t fse_release(void);
 
+/* ---- prepared plans replayed as HIP graphs ---------------------------- */
+
+/* A plan fixes n loss masks and the parameters: blocks, dependency order and
+ * device tables are built once, the masks are copied (the caller may free
+ * them after the call), and the launch sequence is captured in a HIP graph.
+ * Only the persistent schedule can be planned; trace_sel must be NULL.
+ * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+typedef struct fse_plan fse_plan_t;
+fse_status_t fse_plan_create(int32_t n, const fse_mask_t* masks, const fse_params_t* p, fse_plan_t** plan);
+/* Extrapolate n images with the plan's masks: images[i] and outs[i] must have
+ * the size of mask i.  Enqueued on `stream` as one graph launch; executions of
+ * one plan are serialised (each waits until the previous one has finished). */
+fse_status_t fse_plan_execute(fse_plan_t* plan, const fse_image_t* images, fse_image_t* outs, void* stream);
+fse_status_t fse_plan_destroy(fse_plan_t* plan);
+
 /* ---- serving: continuous batching of requests ------------------------- */
 
 typedef struct fse_server fse_server_t;

@@ -222,11 +222,9 @@ struct HostJob {
     RegionPlan plan;
 };
 
-fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
-                       fse_image_t* outs, hipStream_t st) {
-    fse_run_stats_t stats{};
+static fse_status_t check_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                                const fse_image_t* outs, std::vector<ClassCfg>& cls) {
     if (n < 1 || !images || !masks || !outs) return FSE_ERR_INVALID_ARG;
-    std::vector<ClassCfg> cls;
     fse_status_t s = check_params(p, cls);
     if (s != FSE_OK) return s;
     for (int i = 0; i < n; ++i) {
@@ -237,12 +235,34 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
         if (outs[i].width != images[i].width || outs[i].height != images[i].height) return FSE_ERR_INVALID_ARG;
         if (outs[i].data == images[i].data) return FSE_ERR_INVALID_ARG;
     }
+    return FSE_OK;
+}
+
+fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                       fse_image_t* outs, hipStream_t st) {
+    std::vector<ClassCfg> cls;
+    fse_status_t s = check_batch(n, images, masks, p, outs, cls);
+    if (s != FSE_OK) return s;
     Workspace* wsp = workspace_for(st);
     std::lock_guard<std::mutex> lk(wsp->mu);
     Workspace& ws = *wsp;
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return from_hip(e);
+    Prepared P;
+    if ((s = prepare_batch(ws, n, images, masks, p, outs, cls, st, P)) != FSE_OK) return s;
+    if ((s = launch_prepared(ws, P, st, true)) != FSE_OK) return s;
+    ws.last_stream = st;
+    g_last_stats = P.stats;
+    g_last_ws = &ws;
+    return FSE_OK;
+}
 
+fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, const fse_mask_t* masks,
+                           const fse_params_t* p, const fse_image_t* outs, const std::vector<ClassCfg>& cls,
+                           hipStream_t st, Prepared& P) {
+    fse_run_stats_t stats{};
+    fse_status_t s = FSE_OK;
+    hipError_t e = hipSuccess;
     const double t0 = now_ms();
     // ---- masks to the host, regions, plans ---------------------------------
     std::vector<HostJob> jobs;
@@ -423,60 +443,85 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
         max_w = std::max(max_w, J.W);
         max_h = std::max(max_h, J.H);
     }
-    int32_t* counter = misc + 1;
-    e = launch_init_job(a.jobs, (int)jobs.size(), max_w, max_h, counter, a.error, a.degenerate, st);
-    if (e != hipSuccess) return from_hip(e);
-    if (!ws.ev0) {
-        if ((e = hipEventCreate(&ws.ev0)) != hipSuccess) return from_hip(e);
-        if ((e = hipEventCreate(&ws.ev1)) != hipSuccess) return from_hip(e);
-    }
-    if ((e = hipEventRecord(ws.ev0, st)) != hipSuccess) return from_hip(e);
+    a.counter = misc + 1;
     bool wide = false;
     for (auto& c : cls) wide |= (c.M == 64);
     const int nw = wide ? 4 : (p->block_waves > 0 ? p->block_waves : 4);
-    if (ntk > 0) {
-        if (p->schedule == FSE_SCHED_PERSISTENT) {
-            a.counter = counter;
-            // Automatic grid: about twice the average number of blocks that share
-            // a wavefront key.  A dependency chain runs fastest when its blocks
-            // do not share SIMDs with blocks that cannot start yet, so a grid
-            // much larger than the available parallelism only slows the chain.
-            int grid = p->workgroups;
-            if (grid <= 0) {
-                const int64_t par = (ntk + std::max(1, nkeys) - 1) / std::max(1, nkeys);
-                const int64_t want = std::max<int64_t>(64, ((2 * par + 63) / 64) * 64);
-                grid = (int)std::min<int64_t>(want, persistent_grid(nw, p->precision, wide));
+    // Automatic grid: about twice the average number of blocks that share a
+    // wavefront key.  A dependency chain runs fastest when its blocks do not
+    // share SIMDs with blocks that cannot start yet, so a grid much larger than
+    // the available parallelism only slows the chain.
+    int grid = p->workgroups;
+    if (grid <= 0) {
+        const int64_t par = (ntk + std::max(1, nkeys) - 1) / std::max(1, nkeys);
+        const int64_t want = std::max<int64_t>(64, ((2 * par + 63) / 64) * 64);
+        grid = (int)std::min<int64_t>(want, persistent_grid(nw, p->precision, wide));
+    }
+    grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, ntk));
+    if (p->schedule == FSE_SCHED_PER_BLOCK && ntk > 0) {
+        // plain path: one launch per block, raster order of each job
+        std::vector<int32_t> raster(2 * ntk);
+        size_t q = 0;
+        for (size_t j = 0; j < jobs.size(); ++j)
+            for (size_t b = 0; b < jobs[j].plan.key.size(); ++b) {
+                raster[2 * q] = (int32_t)j;
+                raster[2 * q + 1] = (int32_t)b;
+                ++q;
             }
-            grid = (int)std::min<int64_t>(grid, ntk);
-            e = launch_blocks_at(a, nw, p->precision, wide, grid, 0, st);
-        } else if (p->schedule == FSE_SCHED_WAVEFRONT) {
+        std::memcpy(ws.stage + o_tk, raster.data(), (size_t)ntk * 8);
+        if ((e = up(ws.tickets, ws.stage + o_tk, (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
+    }
+    P.a = a;
+    P.n_jobs = (int)jobs.size();
+    P.max_w = max_w;
+    P.max_h = max_h;
+    P.nw = nw;
+    P.wide = wide;
+    P.grid = grid;
+    P.precision = p->precision;
+    P.schedule = p->schedule;
+    P.ntk = ntk;
+    P.kstart = kstart;
+    P.max_key = max_key;
+    P.o_jobs = o_jobs;
+    P.b_jobs = jobs.size() * sizeof(JobDev);
+    P.job_image.clear();
+    for (auto& J : jobs) P.job_image.push_back(J.img);
+    P.stats = stats;
+    return FSE_OK;
+}
+
+fse_status_t launch_prepared(Workspace& ws, Prepared& P, hipStream_t st, bool timed) {
+    hipError_t e = launch_init_job(P.a.jobs, P.n_jobs, P.max_w, P.max_h, P.a.counter, P.a.error, P.a.degenerate, st);
+    if (e != hipSuccess) return from_hip(e);
+    if (timed) {
+        if (!ws.ev0) {
+            if ((e = hipEventCreate(&ws.ev0)) != hipSuccess) return from_hip(e);
+            if ((e = hipEventCreate(&ws.ev1)) != hipSuccess) return from_hip(e);
+        }
+        if ((e = hipEventRecord(ws.ev0, st)) != hipSuccess) return from_hip(e);
+    }
+    LaunchArgs a = P.a;
+    if (P.ntk > 0) {
+        if (P.schedule == FSE_SCHED_PERSISTENT) {
+            e = launch_blocks_at(a, P.nw, P.precision, P.wide, P.grid, 0, st);
+        } else if (P.schedule == FSE_SCHED_WAVEFRONT) {
             a.counter = nullptr;
-            for (int k = 0; k <= max_key && e == hipSuccess; ++k) {
-                const int cnt = kstart[k + 1] - kstart[k];
-                if (cnt > 0) e = launch_blocks_at(a, nw, p->precision, wide, cnt, kstart[k], st);
+            for (int k = 0; k <= P.max_key && e == hipSuccess; ++k) {
+                const int cnt = P.kstart[k + 1] - P.kstart[k];
+                if (cnt > 0) e = launch_blocks_at(a, P.nw, P.precision, P.wide, cnt, P.kstart[k], st);
             }
         } else {
-            // plain path: one launch per block, raster order of each job
             a.counter = nullptr;
-            std::vector<int32_t> raster(2 * ntk);
-            size_t q = 0;
-            for (size_t j = 0; j < jobs.size(); ++j)
-                for (size_t b = 0; b < jobs[j].plan.key.size(); ++b) {
-                    raster[2 * q] = (int32_t)j;
-                    raster[2 * q + 1] = (int32_t)b;
-                    ++q;
-                }
-            std::memcpy(ws.stage + o_tk, raster.data(), (size_t)ntk * 8);
-            if ((e = up(ws.tickets, ws.stage + o_tk, (size_t)ntk * 8)) != hipSuccess) return from_hip(e);
-            for (int64_t k = 0; k < ntk && e == hipSuccess; ++k) e = launch_blocks_at(a, nw, p->precision, wide, 1, (int)k, st);
+            for (int64_t k = 0; k < P.ntk && e == hipSuccess; ++k)
+                e = launch_blocks_at(a, P.nw, P.precision, P.wide, 1, (int)k, st);
         }
         if (e != hipSuccess) return from_hip(e);
     }
-    if ((e = hipEventRecord(ws.ev1, st)) != hipSuccess) return from_hip(e);
-    ws.timed = true;
-    ws.last_stream = st;
-    g_last_stats = stats;
-    g_last_ws = &ws;
+    if (timed) {
+        if ((e = hipEventRecord(ws.ev1, st)) != hipSuccess) return from_hip(e);
+        ws.timed = true;
+    }
     return FSE_OK;
 }
 

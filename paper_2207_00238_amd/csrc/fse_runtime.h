@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/fse.h"
+#include "fse_internal.h"
 
 namespace fse {
 
@@ -41,6 +42,21 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls);
 // one extrapolation call (fse_extrapolate / fse_extrapolate_batch)
 fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
                        fse_image_t* outs, hipStream_t st);
+// A planned batch: device tables uploaded into a workspace, ready to launch.
+struct Prepared {
+    LaunchArgs a{};
+    int n_jobs = 0, max_w = 1, max_h = 1, nw = 4, grid = 1, precision = 0, schedule = 0, max_key = 0;
+    bool wide = false;
+    int64_t ntk = 0;
+    std::vector<int32_t> kstart;
+    size_t o_jobs = 0, b_jobs = 0;  // the JobDev table inside the workspace's pinned staging
+    std::vector<int> job_image;     // image of every job
+    fse_run_stats_t stats{};
+};
+fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, const fse_mask_t* masks,
+                           const fse_params_t* p, const fse_image_t* outs, const std::vector<ClassCfg>& cls,
+                           hipStream_t st, Prepared& P);
+fse_status_t launch_prepared(Workspace& ws, Prepared& P, hipStream_t st, bool timed);
 // statistics of this thread's last call as planned on the host (no device wait)
 void fse_last_stats_nowait(fse_run_stats_t* st);
 Workspace* workspace_for(hipStream_t st);

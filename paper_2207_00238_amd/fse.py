@@ -31,7 +31,7 @@ FSE_MAX_CLASSES = 3
 EXPORTED = [
     "fse_status_string", "fse_params_default", "fse_plan_tiles", "fse_extrapolate", "fse_extrapolate_batch",
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
-    "fse_serve_destroy",
+    "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy",
 ]
 
 
@@ -120,6 +120,12 @@ def lib():
         L.fse_serve_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, P(fse_request_stats_t)]
         L.fse_serve_destroy.restype = st
         L.fse_serve_destroy.argtypes = [ctypes.c_void_p]
+        L.fse_plan_create.restype = st
+        L.fse_plan_create.argtypes = [ctypes.c_int32, P(fse_mask_t), P(fse_params_t), P(ctypes.c_void_p)]
+        L.fse_plan_execute.restype = st
+        L.fse_plan_execute.argtypes = [ctypes.c_void_p, P(fse_image_t), P(fse_image_t), ctypes.c_void_p]
+        L.fse_plan_destroy.restype = st
+        L.fse_plan_destroy.argtypes = [ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -255,3 +261,26 @@ def fse_serve_wait(server, ticket: int, timeout_us: int = -1) -> dict:
 
 def fse_serve_destroy(server) -> None:
     check(lib().fse_serve_destroy(server), "fse_serve_destroy")
+
+
+# ---------------------------------------------------------------------------
+# prepared plans (HIP graph replay)
+# ---------------------------------------------------------------------------
+
+def fse_plan_create(masks, params: fse_params_t):
+    n = len(masks)
+    mks = (fse_mask_t * n)(*[_mask(t) for t in masks])
+    h = ctypes.c_void_p()
+    check(lib().fse_plan_create(n, mks, ctypes.byref(params), ctypes.byref(h)), "fse_plan_create")
+    return h
+
+
+def fse_plan_execute(plan, images, outs, stream=None) -> None:
+    n = len(images)
+    ims = (fse_image_t * n)(*[_image(t) for t in images])
+    ots = (fse_image_t * n)(*[_image(t) for t in outs])
+    check(lib().fse_plan_execute(plan, ims, ots, _stream(stream)), "fse_plan_execute")
+
+
+def fse_plan_destroy(plan) -> None:
+    check(lib().fse_plan_destroy(plan), "fse_plan_destroy")

@@ -90,7 +90,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=8, help="1920x1080 requests per batched step")
+    ap.add_argument("--batch", type=int, default=16, help="1920x1080 requests per batched step")
+    ap.add_argument("--no-autotune", action="store_true", help="use the automatic schedule instead of the autotuner")
+    ap.add_argument("--uhd-images", type=int, default=16,
+                    help="3840x2160 mixed-loss images for the tiled batch measurement (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-block comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workgroups", type=int, default=0)
@@ -136,6 +139,10 @@ def main():
     params = fse.fse_params_default(**common)
 
     # ---- batched step: n_img requests in one persistent launch -------------
+    tuned = None
+    if not args.no_autotune and args.workgroups == 0:
+        params = fse.fse_autotune(imgs, msks, params, outs, stream)
+        tuned = {"block_waves": params.block_waves, "workgroups": params.workgroups}
     for _ in range(max(args.warmup, 1)):
         fse.fse_extrapolate_batch(imgs, msks, params, outs, stream)
     st = fse.fse_last_stats()
@@ -178,15 +185,33 @@ def main():
         "config": {"workload": f"hd: {n_img} requests of 1920x1080, 25% 4x4 blocks + 1% pixels lost, "
                                f"{n_blocks} processing blocks per step, B={B} b={b} M={M} K={K}, rho={wl.rho}, "
                                f"gamma={wl.gamma}, exact raster semantics per request",
-                   "schedule": f"one persistent dependency-driven launch per step, {args.block_waves} waves/block"},
+                   "schedule": f"one persistent dependency-driven launch per step, "
+                               f"{params.block_waves} waves/block, grid {params.workgroups or 'automatic'}"
+                               + (" (autotuned)" if tuned else "")},
         "step_p50_ms": float(np.percentile(step_ms, 50)),
         "step_p99_ms": float(np.percentile(step_ms, 99)),
         "kernel_ms": float(np.mean(kern_ms)),
         "host_plan_ms": float(np.mean(plan_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": traffic,
-                     "kernel": f"k_fse_blocks<{args.block_waves}>", "flops_per_block": flops},
+                     "kernel": f"k_fse_blocks<{params.block_waves}>", "flops_per_block": flops},
     }
+
+    # ---- same masks, new images: prepared plan replayed as a HIP graph -------
+    plan = fse.fse_plan_create(msks, params)
+    try:
+        fse.fse_plan_execute(plan, imgs, outs, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fse.fse_plan_execute(plan, imgs, outs, stream)
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - t0) / args.steps
+        result["graph_replay"] = {"value": n_blocks / dtg, "unit": "blocks/s", "ms_per_step": dtg * 1e3,
+                                  "bitwise_equal_to_batched": bool(torch.equal(outs[0], batched_out0)),
+                                  "note": "masks planned once; each step replays the captured launch"}
+    finally:
+        fse.fse_plan_destroy(plan)
 
     # ---- one request alone ------------------------------------------------
     img, msk, out = imgs[0], msks[0], outs[0]
@@ -231,6 +256,9 @@ def main():
                                     "blocks_executed": s["n_blocks"],
                                     "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole})
 
+    if args.uhd_images > 0:
+        result["uhd_tiled_batch"] = uhd_batch(fse, torch, np, args.uhd_images, args.steps)
+
     if not args.no_precision_sweep:
         result["precision_sweep"] = precision_sweep(fse, torch, np, img, msk, common, wl, K)
 
@@ -254,6 +282,32 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def uhd_batch(fse, torch, np, n, steps):
+    """3840x2160 frames with mixed 8x8 (10 %), 16x16 (5 %) and row (0.5 %)
+    losses (64x64 windows with K = 200 for the 8x8 and 16x16 blocks, 32x32 with
+    K = 100 for the rest), each cut into 64 tiles with stripe d = 32 by the
+    compact tiling, all tiles of all frames in one persistent launch."""
+    from paper_2207_00238_amd import synth
+    dev = torch.device("cuda:0")
+    wls = [synth.workload("uhd", i) for i in range(n)]
+    imgs = [torch.from_numpy(w.image).to(dev) for w in wls]
+    msks = [torch.from_numpy(w.mask).to(dev) for w in wls]
+    outs = [torch.empty_like(t) for t in imgs]
+    p = fse.fse_params_default(classes=wls[0].classes, tiling=fse.FSE_TILED, n_tiles=64, overlap=32, align=16)
+    fse.fse_extrapolate_batch(imgs, msks, p, outs)
+    fse.fse_last_stats()
+    times = []
+    for _ in range(max(1, steps // 2)):
+        t0 = time.perf_counter()
+        fse.fse_extrapolate_batch(imgs, msks, p, outs)
+        s = fse.fse_last_stats()
+        times.append(time.perf_counter() - t0)
+    dt = float(np.mean(times))
+    return {"images": n, "tiles_per_image": 64, "overlap": 32, "blocks_executed": s["n_blocks"],
+            "value": s["n_blocks"] / dt, "unit": "blocks/s (executed, incl. stripe overlap)",
+            "ms_per_step": dt * 1e3, "kernel_ms": s["kernel_ms"], "host_plan_ms": s["host_plan_ms"]}
 
 
 def precision_sweep(fse, torch, np, img, msk, common, wl, K):

@@ -171,6 +171,17 @@ fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const f
  * that call's stream to finish its work. */
 fse_status_t fse_last_stats(fse_run_stats_t* st);
 
+/* Schedule autotuner: runs the given batch (outputs written to outs) with
+ * wave64s per block in {2, 4} (4 when 64x64 windows are present) and
+ * persistent grids of {automatic, 128, 256, 384, 512, 768, 1024, resident
+ * capacity} workgroups, timing each with HIP events on `stream`, and returns
+ * *p with the fastest block_waves and workgroups in *best.  Neither changes
+ * results.  Results are cached in-process per workload signature (sizes,
+ * classes, precision, tiling); a cached signature returns at once.  Requires
+ * the persistent schedule.  Errors as fse_extrapolate_batch. */
+fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                          fse_image_t* outs, void* stream, fse_params_t* best);
+
 /* Free all cached device workspace (waits for the streams that use it). */
 fse_status_t fse_release(void);
 

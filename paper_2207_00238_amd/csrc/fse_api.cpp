@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -627,6 +628,70 @@ fse_status_t fse_last_stats(fse_run_stats_t* st) {
         }
     }
     *st = g_last_stats;
+    return FSE_OK;
+}
+
+fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                          fse_image_t* outs, void* stream, fse_params_t* best) {
+    using namespace fse;
+    if (!best) return FSE_ERR_INVALID_ARG;
+    std::vector<ClassCfg> cls;
+    fse_status_t s = check_batch(n, images, masks, p, outs, cls);
+    if (s != FSE_OK) return s;
+    if (p->schedule != FSE_SCHED_PERSISTENT) return FSE_ERR_INVALID_ARG;
+    // workload signature: sizes, classes, precision, tiling
+    std::string key = std::to_string(p->precision) + "/" + std::to_string(p->tiling) + "/" +
+                      std::to_string(p->n_tiles) + "/" + std::to_string(p->overlap);
+    for (auto& c : cls) key += "/" + std::to_string(c.B) + "," + std::to_string(c.b) + "," + std::to_string(c.K);
+    for (int i = 0; i < n; ++i) key += "/" + std::to_string(images[i].width) + "x" + std::to_string(images[i].height);
+    static std::mutex cache_mu;
+    static std::map<std::string, std::pair<int, int>> cache;
+    *best = *p;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            best->block_waves = it->second.first;
+            best->workgroups = it->second.second;
+            return FSE_OK;
+        }
+    }
+    bool wide = false;
+    for (auto& c : cls) wide |= (c.M == 64);
+    std::vector<int> waves = wide ? std::vector<int>{4} : std::vector<int>{2, 4};
+    double best_ms = 1e30;
+    int best_w = 4, best_g = 0;
+    hipStream_t st = (hipStream_t)stream;
+    for (int w : waves) {
+        const int cap = persistent_grid(w, p->precision, wide);
+        std::vector<int> grids{0};
+        for (int g : {128, 256, 384, 512, 768, 1024})
+            if (g < cap) grids.push_back(g);
+        grids.push_back(cap);
+        for (int g : grids) {
+            fse_params_t q = *p;
+            q.block_waves = w;
+            q.workgroups = g;
+            q.trace_sel = nullptr;
+            double ms = 0;
+            for (int rep = 0; rep < 2; ++rep) {
+                if ((s = run_batch(n, images, masks, &q, outs, st)) != FSE_OK) return s;
+                fse_run_stats_t rs{};
+                if ((s = fse_last_stats(&rs)) != FSE_OK) return s;
+                if (rs.device_error) return FSE_ERR_DEVICE;
+                ms = rs.kernel_ms;
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_w = w;
+                best_g = g;
+            }
+        }
+    }
+    best->block_waves = best_w;
+    best->workgroups = best_g;
+    std::lock_guard<std::mutex> lk(cache_mu);
+    cache[key] = {best_w, best_g};
     return FSE_OK;
 }
 

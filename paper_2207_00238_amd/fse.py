@@ -32,6 +32,7 @@ EXPORTED = [
     "fse_status_string", "fse_params_default", "fse_plan_tiles", "fse_extrapolate", "fse_extrapolate_batch",
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
     "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy",
+    "fse_autotune",
 ]
 
 
@@ -120,6 +121,9 @@ def lib():
         L.fse_serve_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, P(fse_request_stats_t)]
         L.fse_serve_destroy.restype = st
         L.fse_serve_destroy.argtypes = [ctypes.c_void_p]
+        L.fse_autotune.restype = st
+        L.fse_autotune.argtypes = [ctypes.c_int32, P(fse_image_t), P(fse_mask_t), P(fse_params_t), P(fse_image_t),
+                                   ctypes.c_void_p, P(fse_params_t)]
         L.fse_plan_create.restype = st
         L.fse_plan_create.argtypes = [ctypes.c_int32, P(fse_mask_t), P(fse_params_t), P(ctypes.c_void_p)]
         L.fse_plan_execute.restype = st
@@ -284,3 +288,15 @@ def fse_plan_execute(plan, images, outs, stream=None) -> None:
 
 def fse_plan_destroy(plan) -> None:
     check(lib().fse_plan_destroy(plan), "fse_plan_destroy")
+
+
+def fse_autotune(images, masks, params: fse_params_t, outs, stream=None) -> fse_params_t:
+    """Fastest schedule (block_waves, workgroups) for this batch; outs receive results."""
+    n = len(images)
+    ims = (fse_image_t * n)(*[_image(t) for t in images])
+    mks = (fse_mask_t * n)(*[_mask(t) for t in masks])
+    ots = (fse_image_t * n)(*[_image(t) for t in outs])
+    best = fse_params_t()
+    check(lib().fse_autotune(n, ims, mks, ctypes.byref(params), ots, _stream(stream), ctypes.byref(best)),
+          "fse_autotune")
+    return best

@@ -49,3 +49,23 @@ def test_plan_rejects_mismatched_images():
             fse.fse_plan_execute(plan, [img], [torch.empty_like(img)])
     finally:
         fse.fse_plan_destroy(plan)
+
+
+def test_autotune_returns_equivalent_schedule():
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    wl = synth.workload("small")
+    img = torch.from_numpy(wl.image).to(dev)
+    msk = torch.from_numpy(wl.mask).to(dev)
+    p = fse.fse_params_default(classes=wl.classes)
+    out_a = torch.empty_like(img)
+    best = fse.fse_autotune([img], [msk], p, [out_a])
+    assert best.block_waves in (2, 4) and best.workgroups >= 0
+    out_b = torch.empty_like(img)
+    fse.fse_extrapolate(img, msk, best, out_b)
+    torch.cuda.synchronize()
+    assert torch.equal(out_a, out_b)
+    # cached: the second call returns the same schedule
+    best2 = fse.fse_autotune([img], [msk], p, [out_a])
+    assert (best2.block_waves, best2.workgroups) == (best.block_waves, best.workgroups)

@@ -63,14 +63,27 @@ hipError_t launch_init_job(const JobDev* jobs_dev, int n_jobs, int max_w, int ma
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// Loads of data that no kernel of the launch writes (job descriptors, block
+// descriptors).  Through the constant address space a uniform address becomes
+// a scalar load kept in SGPRs instead of repeated vector loads.
+template <class T>
+__device__ __forceinline__ T const_load(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) T*)(p);
+#else
+    return *p;  // host pass: never executed, address spaces do not exist there
+#endif
+}
+
 __device__ __forceinline__ int ld_acquire(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // (e, idx) pair ordering: larger energy first, smaller index on equal energy
 __device__ __forceinline__ bool better(double e1, int i1, double e0, int i0) {
-    return e1 > e0 || (e1 == e0 && i1 < i0);
+    return (e1 > e0) | ((e1 == e0) & (i1 < i0));
 }
+
 
 __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, int by0, int bx0, int by1,
                                            int bx1) {
@@ -90,8 +103,17 @@ struct SharedHead {
     double twc32[32], tws32[32];
     double twc64[64], tws64[64];
     double part[4];
-    double4 sl[2][4];  // per wave: energy, Re R, Im R, index
+    // per step (double-buffered) and wave: the wave winner's energy, spectrum
+    // index and coefficient
+    double sE[2][4];
+    int32_t sI[2][4];
+    double2 sA[2][4];
     int job, blk, wait_fail;
+    uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
+    // coefficient list of the K steps (written during the steps, read by the
+    // synthesis)
+    double car[kMaxK], cai[kMaxK];
+    int32_t cidx[kMaxK];
 };
 
 template <int NBUF>
@@ -122,20 +144,53 @@ __device__ __forceinline__ unsigned wave_umax(unsigned v) {
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Exact maximum of a non-negative double over the wave (uniform result).
-__device__ __forceinline__ double wave_max_nonneg(double v) {
-    const unsigned hi = (unsigned)__double2hiint(v);
+// Lane holding the wave's largest non-negative energy; among equal energies
+// the lane whose spectrum index is smallest.  The high words decide in one
+// DPP pass unless several lanes share the largest high word.
+template <class IndexFn>
+__device__ __forceinline__ int wave_argmax_lane(double e, IndexFn idx_of) {
+    const unsigned hi = (unsigned)__double2hiint(e);
     const unsigned mhi = wave_umax(hi);
-    const bool cand = hi == mhi;
-    unsigned mlo = (unsigned)__double2loint(v);
-    if (__popcll(__ballot(cand)) > 1) {
-        mlo = wave_umax(cand ? (unsigned)__double2loint(v) : 0u);
-    } else {
-        const int l = __ffsll((unsigned long long)__ballot(cand)) - 1;
-        mlo = (unsigned)__builtin_amdgcn_readlane((int)mlo, l);
+    bool cand = hi == mhi;
+    uint64_t bal = __ballot(cand);
+    if (__popcll(bal) > 1) {
+        const unsigned lo = (unsigned)__double2loint(e);
+        const unsigned mlo = wave_umax(cand ? lo : 0u);
+        cand = cand && lo == mlo;
+        bal = __ballot(cand);
+        if (__popcll(bal) > 1) {
+            // exact tie between lanes: the smallest spectrum index among them
+            const int idx = idx_of();
+            int best = cand ? idx : 0x7fffffff;
+            for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
+            bal = __ballot(cand && idx == best);
+        }
     }
-    return __hiloint2double((int)mhi, (int)mlo);
+    return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
 }
+
+template <class IndexFn>
+__device__ __forceinline__ int wave_argmax_lane(float e, IndexFn idx_of) {
+    const unsigned k = __float_as_uint(e);
+    const bool cand = k == wave_umax(k);
+    uint64_t bal = __ballot(cand);
+    if (__popcll(bal) > 1) {
+        const int idx = idx_of();
+        int best = cand ? idx : 0x7fffffff;
+        for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
+        bal = __ballot(cand && idx == best);
+    }
+    return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
+}
+
+__device__ __forceinline__ double readlane_t(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float readlane_t(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 
 
 // ---------------------------------------------------------------------------
@@ -236,14 +291,13 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     constexpr int MASK = M - 1;
     constexpr int LOGM = (M == 32) ? 5 : 6;
     constexpr bool DUP = (M == 32);           // weight spectrum rows duplicated
-    constexpr int NSLOT = (kMaxK + NT - 1) / NT;  // coefficient slots per thread
     const double* twc = (M == 32) ? H.twc32 : H.twc64;
     const double* tws = (M == 32) ? H.tws32 : H.tws64;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = t >> 6;
     const int ti0 = TM::ti0(wv), tj0 = TM::tj0(wv);
-    const int4 d = J.desc[blk];
+    const int4 d = const_load(J.desc + blk);
     const ClassDev& C = a.cls[d.z];
     const int B = C.B, b = C.b, K = C.K;
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
@@ -257,20 +311,24 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         const int m = (t >> LOGM) + RS * j, n = t & MASK;
         const int y = wy + m, x = wx + n;
         double w = 0.0, v = 0.0;
+        bool lost = false;
         if (y >= 0 && y < J.H && x >= 0 && x < J.W) {
+            // all four loads in flight together; the status picks afterwards
             const int64_t q = (int64_t)y * J.W + x;
             const uint8_t st = J.status[q];
-            if (st == kKnown) {
-                w = C.wtab[m * M + n];
-                v = (double)J.img[(int64_t)(J.oy + y) * J.img_pitch + (J.ox + x)];
-            } else if (st == kRecon) {
-                w = a.delta * C.wtab[m * M + n];
-                v = J.recon[q];
-            }
+            const double wt = C.wtab[m * M + n];
+            const double sv = (double)J.img[(int64_t)(J.oy + y) * J.img_pitch + (J.ox + x)];
+            const double rv = J.recon[q];
+            w = st == kKnown ? wt : (st == kRecon ? a.delta * wt : 0.0);
+            v = st == kKnown ? sv : (st == kRecon ? rv : 0.0);
+            lost = st == kLost;
         }
         Xs[m * LD + n] = (T)(w * v);
         Xw[m * LD + n] = (T)w;
         wsum += w;
+        // lost pixels of the core, synthesised at the end (only this block
+        // writes them, so the status cannot change in between)
+        if (m >= b && m < b + B && n >= b && n < b + B) H.lost[(m - b) * B + (n - b)] = lost;
     }
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
     if (lane == 0) H.part[wv] = wsum;
@@ -394,86 +452,105 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // ---- K greedy steps ----------------------------------------------------
     // lane element e = (row tile ci_, r, column tile cj); its row is
     // (ti0+ci_)*16 + lk + 4r (FP64) or (ti0+ci_)*16 + 4 lk + r (FP32, BF16),
-    // column (tj0+cj)*16 + li; the index k*M + l increases with e
+    // column (tj0+cj)*16 + li; the index k*M + l increases with e.
+    // Per step: a first-index maximum inside the lane, the wave's winner lane
+    // from a DPP maximum, the winner's values broadcast with readlane; with
+    // several waves one LDS exchange (one barrier) combines the wave winners;
+    // then the shifted weight spectrum is gathered from LDS for the update.
     constexpr int ROWK = F64 ? 1 : 4;  // row step per lk
     constexpr int ROWR = F64 ? 4 : 1;  // row step per r
-    const bool live = W0 > 0.0;
+    // uniform across the block: lets the loop run under scalar control
+    const bool live = __builtin_amdgcn_readfirstlane((int)(W0 > 0.0)) != 0;
+    const int nsteps = live ? __builtin_amdgcn_readfirstlane(K) : 0;
     const double g = live ? a.gamma / W0 : 0.0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
-    int c_idx[NSLOT];
-    double c_ar[NSLOT], c_ai[NSLOT];
+    // spectrum index of element e of lane ln
+    auto elem_index_at = [&](int e, int ln) {
+        const int jr = (e / NTJ) & 3, jci = e / (4 * NTJ), jcj = e % NTJ;
+        return ((ti0 + jci) * 16 + ROWK * (ln >> 4) + ROWR * jr) * M + (tj0 + jcj) * 16 + (ln & 15);
+    };
+    auto elem_index = [&](int e) { return elem_index_at(e, lane); };
+    for (int it = 0; it < nsteps; ++it) {
+        // first-index maximum over the lane's elements (pairwise tree over
+        // increasing index: the right operand wins only when strictly larger)
+        T ev[EPT];
+        int jv[EPT];
 #pragma unroll
-    for (int q = 0; q < NSLOT; ++q) {
-        c_idx[q] = 0;
-        c_ar[q] = 0.0;
-        c_ai[q] = 0.0;
-    }
-    for (int it = 0; it < K && live; ++it) {
-        // local maximiser: strict '>' over increasing index keeps the first
-        T lm = rr[0] * rr[0] + ri[0] * ri[0];
-        int jl = 0;
-#pragma unroll
-        for (int j = 1; j < EPT; ++j) {
-            const T e = rr[j] * rr[j] + ri[j] * ri[j];
-            const bool take = e > lm;
-            lm = take ? e : lm;
-            jl = take ? j : jl;
+        for (int j = 0; j < EPT; ++j) {
+            ev[j] = rr[j] * rr[j] + ri[j] * ri[j];
+            jv[j] = j;
         }
-        T wm;
-        if constexpr (F64)
-            wm = wave_max_nonneg(lm);
-        else
-            wm = __uint_as_float(wave_umax(__float_as_uint(lm)));
-        const uint64_t hit = __ballot(lm == wm);
-        // spectrum index of this lane's local maximiser
-        const int jr = (jl / NTJ) & 3, jci = jl / (4 * NTJ), jcj = jl % NTJ;
-        const int my_idx = ((ti0 + jci) * 16 + ROWK * lk + ROWR * jr) * M + (tj0 + jcj) * 16 + li;
-        int wl = __ffsll((unsigned long long)hit) - 1;
-        if (__popcll(hit) > 1) {
-            // exact tie between lanes: the smallest spectrum index among them
-            int best = (lm == wm) ? my_idx : 0x7fffffff;
-            for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
-            const uint64_t h2 = __ballot((lm == wm) & (my_idx == best));
-            wl = __ffsll((unsigned long long)h2) - 1;
-        }
-        const int p = it & 1;
-        if (lane == wl) {
-            T vr = rr[0], vi = ri[0];
 #pragma unroll
-            for (int j = 1; j < EPT; ++j) {
-                vr = (jl == j) ? rr[j] : vr;
-                vi = (jl == j) ? ri[j] : vi;
+        for (int st = 1; st < EPT; st <<= 1) {
+#pragma unroll
+            for (int j = 0; j + st < EPT; j += 2 * st) {
+                const bool take = ev[j + st] > ev[j];
+                ev[j] = take ? ev[j + st] : ev[j];
+                jv[j] = take ? jv[j + st] : jv[j];
             }
-            H.sl[p][wv] = make_double4((double)wm, (double)vr, (double)vi, (double)my_idx);
         }
-        __syncthreads();  // slot visible to every lane (a single wave keeps LDS order)
-        double4 c[NW];
+        const T lm = ev[0];
+        const int jl = jv[0];
+        // winner lane of the wave: largest energy, then smallest index
+        const int wl = wave_argmax_lane(lm, [&] { return elem_index(jl); });
+        // its element, index and coefficient, read from that lane (the
+        // element number is uniform, so the register is picked by a scalar
+        // branch)
+        const int sjl = __builtin_amdgcn_readlane(jl, wl);
+        T vr = 0, vi = 0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) c[q] = H.sl[p][q];
-        double E = c[0].x, Rr = c[0].y, Ri = c[0].z, fi = c[0].w;
-#pragma unroll
-        for (int q = 1; q < NW; ++q) {
-            const bool take = (c[q].x > E) | ((c[q].x == E) & (c[q].w < fi));
-            E = take ? c[q].x : E;
-            Rr = take ? c[q].y : Rr;
-            Ri = take ? c[q].z : Ri;
-            fi = take ? c[q].w : fi;
+        for (int j = 0; j < EPT; ++j) {
+            if (sjl == j) {
+                vr = readlane_t(rr[j], wl);
+                vi = readlane_t(ri[j], wl);
+            }
         }
-        const int IDX = (int)fi;
-        const double ar = g * Rr;
-        const double ai = g * Ri;
-        // coefficient of step it is kept by thread it % NT in slot it / NT
-        const bool mine = t == (it % NT);
+        const int widx = elem_index_at(sjl, wl);
+        const double war = g * (double)vr;
+        const double wai = g * (double)vi;
+        int IDX;
+        double ar, ai;
+        if constexpr (NW == 1) {
+            IDX = widx;
+            ar = war;
+            ai = wai;
+        } else {
+            const int p = it & 1;
+            const double wE = (double)readlane_t(lm, wl);
+            if (lane == 0) {
+                H.sE[p][wv] = wE;
+                H.sI[p][wv] = widx;
+                H.sA[p][wv] = make_double2(war, wai);
+            }
+            __syncthreads();  // slots visible to every wave
+            // winner among the waves: larger energy, then smaller index
+            // (pairwise tree); only energies and indices are read here
+            double e[NW];
+            int ix[NW], wq[NW];
 #pragma unroll
-        for (int q = 0; q < NSLOT; ++q) {
-            const bool sel = mine & ((it / NT) == q);
-            c_idx[q] = sel ? IDX : c_idx[q];
-            c_ar[q] = sel ? ar : c_ar[q];
-            c_ai[q] = sel ? ai : c_ai[q];
+            for (int q = 0; q < NW; ++q) {
+                e[q] = H.sE[p][q];
+                ix[q] = H.sI[p][q];
+                wq[q] = q;
+            }
+#pragma unroll
+            for (int st = 1; st < NW; st <<= 1) {
+#pragma unroll
+                for (int q = 0; q + st < NW; q += 2 * st) {
+                    const bool take = better(e[q + st], ix[q + st], e[q], ix[q]);
+                    e[q] = take ? e[q + st] : e[q];
+                    ix[q] = take ? ix[q + st] : ix[q];
+                    wq[q] = take ? wq[q + st] : wq[q];
+                }
+            }
+            IDX = __builtin_amdgcn_readfirstlane(ix[0]);
+            const double2 al = H.sA[p][__builtin_amdgcn_readfirstlane(wq[0])];
+            ar = al.x;
+            ai = al.y;
         }
-        if (trace && t == 0) trace[it] = IDX;
+        // the shifted weight spectrum for this lane's elements
         const int u = IDX >> LOGM, v = IDX & MASK;
-        const T tar = (T)ar, tai = (T)ai;
+        T wr[EPT], wi[EPT];
 #pragma unroll
         for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
@@ -486,28 +563,29 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                     // DUP: rows row0 + M + ROWR r lie in [1, 2M) of the duplicated table
                     const T* w = DUP ? (Wd + (((row0 + M) << LOGM) + col) * 2 + r * (ROWR * M * 2))
                                      : (Wd + ((((row0 + ROWR * r) & MASK) << LOGM) + col) * 2);
-                    const T wr = w[0], wi = w[1];
-                    rr[e] = fma(-tar, wr, fma(tai, wi, rr[e]));
-                    ri[e] = fma(-tar, wi, fma(-tai, wr, ri[e]));
+                    wr[e] = w[0];
+                    wi[e] = w[1];
                 }
             }
         }
-    }
-    if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
-    __syncthreads();  // the weight spectrum is dead: the coefficient list takes its place
-    double* car = buf;
-    double* cai = buf + kMaxK;
-    int* cidx = reinterpret_cast<int*>(buf + 2 * kMaxK);
+        if (t == 0) {
+            H.car[it] = ar;
+            H.cai[it] = ai;
+            H.cidx[it] = IDX;
+        }
+        if (trace && t == 0) trace[it] = IDX;
+        const T tar = (T)ar, tai = (T)ai;
 #pragma unroll
-    for (int q = 0; q < NSLOT; ++q) {
-        const int it = q * NT + t;
-        if (it < K) {
-            cidx[it] = c_idx[q];
-            car[it] = c_ar[q];
-            cai[it] = c_ai[q];
+        for (int e = 0; e < EPT; ++e) {
+            rr[e] = fma(-tar, wr[e], fma(tai, wi[e], rr[e]));
+            ri[e] = fma(-tar, wi[e], fma(-tai, wr[e], ri[e]));
         }
     }
-    __syncthreads();
+    if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
+    __syncthreads();  // the coefficient list is complete
+    const double* car = H.car;
+    const double* cai = H.cai;
+    const int32_t* cidx = H.cidx;
 
     // ---- synthesis at the block's lost pixels ------------------------------
     // gs threads per pixel, each summing every gs-th step; B*B pixels
@@ -527,17 +605,13 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             }
         }
         for (int off = gs >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
-        if (sub == 0) {
+        if (sub == 0 && H.lost[px]) {
             const int y = d.x + py, x = d.y + pxx;
-            if (y < J.H && x < J.W) {
-                const int64_t q = (int64_t)y * J.W + x;
-                if (J.status[q] == kLost) {
-                    J.recon[q] = val;
-                    J.status[q] = kRecon;
-                    if (y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
-                        J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
-                }
-            }
+            const int64_t q = (int64_t)y * J.W + x;
+            J.recon[q] = val;
+            J.status[q] = kRecon;
+            if (y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
+                J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
         }
     }
     // make this wave's pixel stores visible device-wide before the block is
@@ -552,8 +626,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S) {
-    const int4 d = J.desc[blk];
-    const int4 lb = J.lbox[blk];
+    const int4 d = const_load(J.desc + blk);
+    const int4 lb = const_load(J.lbox + blk);
     const ClassDev& Cj = a.cls[d.z];
     const int Bm = a.Bmin;
     // fine cells that may hold an interacting block
@@ -634,9 +708,9 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blo
             H.wait_fail = 0;
         }
         __syncthreads();
-        const int job = H.job, blk = H.blk;
+        const int job = __builtin_amdgcn_readfirstlane(H.job), blk = __builtin_amdgcn_readfirstlane(H.blk);
         if (job < 0) break;
-        const JobDev& J = a.jobs[job];
+        const JobDev J = const_load(a.jobs + job);
         wait_predecessors<64 * NW>(a, J, blk, H);
         if constexpr (WIDE) {
             if (a.cls[J.desc[blk].z].M == 64)

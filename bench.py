@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="length of the served Poisson stream (0 = skip)")
     ap.add_argument("--no-precision-sweep", action="store_true", help="skip the FP32 / BF16x3 comparison")
     ap.add_argument("--serve-rate", type=float, default=16.0, help="requests per second of the served stream")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="measure the batched step only (for profiler runs): no secondary measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 256 MiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -196,6 +198,10 @@ def main():
                      "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": traffic,
                      "kernel": f"k_fse_blocks<{params.block_waves}>", "flops_per_block": flops},
     }
+
+    if args.only_batched:
+        print(json.dumps(result), flush=True)
+        return
 
     # ---- same masks, new images: prepared plan replayed as a HIP graph -------
     plan = fse.fse_plan_create(msks, params)

@@ -79,10 +79,6 @@ __device__ __forceinline__ int ld_acquire(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// (e, idx) pair ordering: larger energy first, smaller index on equal energy
-__device__ __forceinline__ bool better(double e1, int i1, double e0, int i0) {
-    return (e1 > e0) | ((e1 == e0) & (i1 < i0));
-}
 
 
 __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, int by0, int bx0, int by1,
@@ -105,8 +101,7 @@ struct SharedHead {
     double part[4];
     // per step (double-buffered) and wave: the wave winner's energy, spectrum
     // index and coefficient
-    double sE[2][4];
-    int32_t sI[2][4];
+    double2 sK[2][4];  // energy, index (low word)
     double2 sA[2][4];
     int job, blk, wait_fail;
     uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
@@ -179,6 +174,37 @@ __device__ __forceinline__ int wave_argmax_lane(float e, IndexFn idx_of) {
         int best = cand ? idx : 0x7fffffff;
         for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
         bal = __ballot(cand && idx == best);
+    }
+    return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
+}
+
+// Winner among NW <= 4 wave slots held by lanes 0..NW-1 (energy e >= 0,
+// index idx): largest energy, then smallest index.  Maxima within the quad
+// by DPP; lanes >= NW are ignored.
+template <int NW>
+__device__ __forceinline__ int slot_winner(double e, int idx) {
+    constexpr unsigned long long SM = (1ull << NW) - 1;
+    auto quad_umax = [](unsigned v) {
+        if constexpr (NW >= 2) v = dpp_umax_step<0xB1, 0xF, 0xF>(v);  // quad_perm [1,0,3,2]
+        if constexpr (NW >= 4) v = dpp_umax_step<0x4E, 0xF, 0xF>(v);  // quad_perm [2,3,0,1]
+        return (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+    };
+    const unsigned hi = (unsigned)__double2hiint(e);
+    bool cand = hi == quad_umax(hi);
+    uint64_t bal = __ballot(cand) & SM;
+    // (each DPP maximum is taken with every lane active: evaluated before
+    // the lane's own condition, never under it)
+    if (__popcll(bal) > 1) {
+        const unsigned lo = (unsigned)__double2loint(e);
+        const unsigned mlo = quad_umax(cand ? lo : 0u);
+        cand = cand && lo == mlo;
+        bal = __ballot(cand) & SM;
+        if (__popcll(bal) > 1) {
+            // equal energies: the smallest index (as a maximum of its complement)
+            const unsigned inv = cand ? ~(unsigned)idx : 0u;
+            const unsigned minv = quad_umax(inv);
+            bal = __ballot(cand && inv == minv) & SM;
+        }
     }
     return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
 }
@@ -518,33 +544,17 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             const int p = it & 1;
             const double wE = (double)readlane_t(lm, wl);
             if (lane == 0) {
-                H.sE[p][wv] = wE;
-                H.sI[p][wv] = widx;
+                H.sK[p][wv] = make_double2(wE, __hiloint2double(0, widx));
                 H.sA[p][wv] = make_double2(war, wai);
             }
             __syncthreads();  // slots visible to every wave
-            // winner among the waves: larger energy, then smaller index
-            // (pairwise tree); only energies and indices are read here
-            double e[NW];
-            int ix[NW], wq[NW];
-#pragma unroll
-            for (int q = 0; q < NW; ++q) {
-                e[q] = H.sE[p][q];
-                ix[q] = H.sI[p][q];
-                wq[q] = q;
-            }
-#pragma unroll
-            for (int st = 1; st < NW; st <<= 1) {
-#pragma unroll
-                for (int q = 0; q + st < NW; q += 2 * st) {
-                    const bool take = better(e[q + st], ix[q + st], e[q], ix[q]);
-                    e[q] = take ? e[q + st] : e[q];
-                    ix[q] = take ? ix[q + st] : ix[q];
-                    wq[q] = take ? wq[q + st] : wq[q];
-                }
-            }
-            IDX = __builtin_amdgcn_readfirstlane(ix[0]);
-            const double2 al = H.sA[p][__builtin_amdgcn_readfirstlane(wq[0])];
+            // winner among the waves (larger energy, then smaller index):
+            // lane q < NW reads the slot of wave q and the lanes pick it like
+            // the wave winner, on a quad instead of the whole wave
+            const double2 sk = H.sK[p][lane & (NW - 1)];
+            const int wq = slot_winner<NW>(sk.x, __double2loint(sk.y));
+            IDX = __builtin_amdgcn_readlane(__double2loint(sk.y), wq);
+            const double2 al = H.sA[p][wq];
             ar = al.x;
             ai = al.y;
         }

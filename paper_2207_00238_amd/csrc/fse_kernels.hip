@@ -75,9 +75,16 @@ __device__ __forceinline__ T const_load(const T* p) {
 #endif
 }
 
-__device__ __forceinline__ int ld_acquire(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Completion flags are polled with relaxed loads; one acquire fence follows
+// the wait.  (An acquire load per poll would invalidate caches on every
+// iteration of the wait.)
+__device__ __forceinline__ int ld_flag(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// s_waitcnt vmcnt(0): wait until this wave's vector memory operations have
+// completed (expcnt and lgkmcnt left alone)
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 
 
@@ -624,10 +631,11 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                 J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
         }
     }
-    // make this wave's pixel stores visible device-wide before the block is
-    // published (the completion flag is set by one thread after a barrier)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();  // the coefficient list is read before the next block reuses the area
+    // every wave's pixel stores complete before the barrier; the release
+    // fence of the publishing thread after it then covers them (one cache
+    // write-back per block instead of one per wave)
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    __syncthreads();  // also: the coefficient list is read before the next block reuses the area
 }
 
 // ---------------------------------------------------------------------------
@@ -664,9 +672,9 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
         const bool e2 = boxes_meet(lb.x, lb.y, lb.z, lb.w, di.x - Ci.b, di.y - Ci.b, di.x + Ci.B + Ci.b,
                                    di.y + Ci.B + Ci.b);
         if (!(e1 || e2)) continue;
-        if (ld_acquire(&J.done[i]) == 0) {
+        if (ld_flag(&J.done[i]) == 0) {
             const uint64_t t0 = wall_clock64();
-            while (ld_acquire(&J.done[i]) == 0) {
+            while (ld_flag(&J.done[i]) == 0) {
                 __builtin_amdgcn_s_sleep(2);
                 if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
                     S.wait_fail = 1;
@@ -676,8 +684,12 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
             }
         }
     }
+    // the flags read above were all set: one acquire fence (it invalidates
+    // the CU's and the L2's stale lines for every wave of the workgroup),
+    // ordered before the other waves' loads by the barrier after it
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -733,7 +745,7 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blo
         __syncthreads();
         if (t == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(&J.done[blk], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&J.done[blk], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!a.counter) break;
         __syncthreads();

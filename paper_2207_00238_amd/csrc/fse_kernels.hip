@@ -497,21 +497,24 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const int nsteps = live ? __builtin_amdgcn_readfirstlane(K) : 0;
     const double g = live ? a.gamma / W0 : 0.0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
-    // spectrum index of element e of lane ln
-    auto elem_index_at = [&](int e, int ln) {
+    // spectrum index of lane element e = lane_idx + elem_offset(e)
+    const int lane_idx = (ti0 * 16 + ROWK * lk) * M + tj0 * 16 + li;
+    auto elem_offset = [](int e) {
         const int jr = (e / NTJ) & 3, jci = e / (4 * NTJ), jcj = e % NTJ;
-        return ((ti0 + jci) * 16 + ROWK * (ln >> 4) + ROWR * jr) * M + (tj0 + jcj) * 16 + (ln & 15);
+        return (jci * 16 + ROWR * jr) * M + jcj * 16;
     };
-    auto elem_index = [&](int e) { return elem_index_at(e, lane); };
     for (int it = 0; it < nsteps; ++it) {
         // first-index maximum over the lane's elements (pairwise tree over
-        // increasing index: the right operand wins only when strictly larger)
-        T ev[EPT];
-        int jv[EPT];
+        // increasing index: the right operand wins only when strictly larger);
+        // the tree carries the element's spectrum index and value
+        T ev[EPT], vr[EPT], vi[EPT];
+        int ix[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             ev[j] = rr[j] * rr[j] + ri[j] * ri[j];
-            jv[j] = j;
+            vr[j] = rr[j];
+            vi[j] = ri[j];
+            ix[j] = lane_idx + elem_offset(j);
         }
 #pragma unroll
         for (int st = 1; st < EPT; st <<= 1) {
@@ -519,40 +522,26 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             for (int j = 0; j + st < EPT; j += 2 * st) {
                 const bool take = ev[j + st] > ev[j];
                 ev[j] = take ? ev[j + st] : ev[j];
-                jv[j] = take ? jv[j + st] : jv[j];
+                ix[j] = take ? ix[j + st] : ix[j];
+                vr[j] = take ? vr[j + st] : vr[j];
+                vi[j] = take ? vi[j + st] : vi[j];
             }
         }
         const T lm = ev[0];
-        const int jl = jv[0];
         // winner lane of the wave: largest energy, then smallest index
-        const int wl = wave_argmax_lane(lm, [&] { return elem_index(jl); });
-        // its element, index and coefficient, read from that lane (the
-        // element number is uniform, so the register is picked by a scalar
-        // branch)
-        const int sjl = __builtin_amdgcn_readlane(jl, wl);
-        T vr = 0, vi = 0;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (sjl == j) {
-                vr = readlane_t(rr[j], wl);
-                vi = readlane_t(ri[j], wl);
-            }
-        }
-        const int widx = elem_index_at(sjl, wl);
-        const double war = g * (double)vr;
-        const double wai = g * (double)vi;
+        const int wl = wave_argmax_lane(lm, [&] { return ix[0]; });
         int IDX;
         double ar, ai;
         if constexpr (NW == 1) {
-            IDX = widx;
-            ar = war;
-            ai = wai;
+            IDX = __builtin_amdgcn_readlane(ix[0], wl);
+            ar = g * (double)readlane_t(vr[0], wl);
+            ai = g * (double)readlane_t(vi[0], wl);
         } else {
             const int p = it & 1;
-            const double wE = (double)readlane_t(lm, wl);
-            if (lane == 0) {
-                H.sK[p][wv] = make_double2(wE, __hiloint2double(0, widx));
-                H.sA[p][wv] = make_double2(war, wai);
+            // the winner lane publishes its own energy, index and coefficient
+            if (lane == wl) {
+                H.sK[p][wv] = make_double2((double)lm, __hiloint2double(0, ix[0]));
+                H.sA[p][wv] = make_double2(g * (double)vr[0], g * (double)vi[0]);
             }
             __syncthreads();  // slots visible to every wave
             // winner among the waves (larger energy, then smaller index):

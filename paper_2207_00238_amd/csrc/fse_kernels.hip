@@ -528,20 +528,25 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             }
         }
         const T lm = ev[0];
+        // the lane's candidate coefficient, formed before the wave reduction
+        // so that it is ready when the winner lane publishes it (the empty
+        // asm keeps it from being sunk into the winner's branch)
+        double car_l = g * (double)vr[0], cai_l = g * (double)vi[0];
+        asm volatile("" : "+v"(car_l), "+v"(cai_l));
         // winner lane of the wave: largest energy, then smallest index
         const int wl = wave_argmax_lane(lm, [&] { return ix[0]; });
         int IDX;
         double ar, ai;
         if constexpr (NW == 1) {
             IDX = __builtin_amdgcn_readlane(ix[0], wl);
-            ar = g * (double)readlane_t(vr[0], wl);
-            ai = g * (double)readlane_t(vi[0], wl);
+            ar = readlane_t(car_l, wl);
+            ai = readlane_t(cai_l, wl);
         } else {
             const int p = it & 1;
             // the winner lane publishes its own energy, index and coefficient
             if (lane == wl) {
                 H.sK[p][wv] = make_double2((double)lm, __hiloint2double(0, ix[0]));
-                H.sA[p][wv] = make_double2(g * (double)vr[0], g * (double)vi[0]);
+                H.sA[p][wv] = make_double2(car_l, cai_l);
             }
             __syncthreads();  // slots visible to every wave
             // winner among the waves (larger energy, then smaller index):
@@ -574,17 +579,19 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                 }
             }
         }
-        if (t == 0) {
-            H.car[it] = ar;
-            H.cai[it] = ai;
-            H.cidx[it] = IDX;
-        }
-        if (trace && t == 0) trace[it] = IDX;
         const T tar = (T)ar, tai = (T)ai;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             rr[e] = fma(-tar, wr[e], fma(tai, wi[e], rr[e]));
             ri[e] = fma(-tar, wi[e], fma(-tai, wr[e], ri[e]));
+        }
+        // the step's coefficient, recorded off the critical path (read only
+        // after the loop)
+        if (t == 0) {
+            H.car[it] = ar;
+            H.cai[it] = ai;
+            H.cidx[it] = IDX;
+            if (trace) trace[it] = IDX;
         }
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);

@@ -98,6 +98,8 @@ void Workspace::free_all() {
     if (ev1) hipEventDestroy(ev1);
     ev0 = ev1 = nullptr;
     timed = false;
+    std::deque<RegionPlan>().swap(plans);
+    std::vector<PlanScratch>().swap(plan_scratch);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,7 +222,7 @@ struct HostJob {
     int img;             // index of the image in the batch
     int ox, oy, W, H;    // region
     int cx0, cy0, cx1, cy1;
-    RegionPlan plan;
+    RegionPlan* plan;  // kept in the workspace between calls (memory reuse)
 };
 
 static fse_status_t check_batch(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
@@ -288,7 +290,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     for (int i = 0; i < n; ++i) {
         const int W = images[i].width, H = images[i].height;
         if (p->tiling == FSE_WHOLE) {
-            HostJob J{i, 0, 0, W, H, 0, 0, W, H, {}};
+            HostJob J{i, 0, 0, W, H, 0, 0, W, H, nullptr};
             jobs.push_back(std::move(J));
         } else {
             std::vector<fse_tile_t> tiles(p->n_tiles);
@@ -296,38 +298,42 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
             if (s != FSE_OK) return s;
             for (auto& T : tiles) {
                 if (T.w <= 0 || T.h <= 0) continue;
-                HostJob J{i, T.ox, T.oy, T.ow, T.oh, T.x - T.ox, T.y - T.oy, T.x - T.ox + T.w, T.y - T.oy + T.h, {}};
+                HostJob J{i, T.ox, T.oy, T.ow, T.oh, T.x - T.ox, T.y - T.oy, T.x - T.ox + T.w, T.y - T.oy + T.h, nullptr};
                 jobs.push_back(std::move(J));
             }
         }
     }
+    // plans and planning scratch live in the workspace (memory reused)
+    while (ws.plans.size() < jobs.size()) ws.plans.emplace_back();
+    if (ws.plan_scratch.size() < jobs.size()) ws.plan_scratch.resize(jobs.size());
+    for (size_t j = 0; j < jobs.size(); ++j) jobs[j].plan = &ws.plans[j];
     std::vector<uint8_t> plan_ok(jobs.size(), 1);
     parallel_for(jobs.size(), [&](size_t j) {
         HostJob& J = jobs[j];
         const uint8_t* mk = ws.host_mask + moff[J.img] + (size_t)J.oy * images[J.img].width + J.ox;
-        plan_ok[j] = plan_region(mk, images[J.img].width, J.W, J.H, cls, J.plan);
+        plan_ok[j] = plan_region(mk, images[J.img].width, J.W, J.H, cls, *J.plan, ws.plan_scratch[j]);
     });
     for (size_t j = 0; j < jobs.size(); ++j) {
         if (!plan_ok[j]) return FSE_ERR_INVALID_ARG;
-        stats.n_blocks += (int64_t)(jobs[j].plan.desc.size() / 4);
+        stats.n_blocks += (int64_t)(jobs[j].plan->desc.size() / 4);
     }
-    for (auto& J : jobs) stats.n_lost_pixels += J.plan.lost_pixels;
+    for (auto& J : jobs) stats.n_lost_pixels += J.plan->lost_pixels;
     stats.n_jobs = (int64_t)jobs.size();
 
     // ---- tickets: all blocks of all jobs ordered by wavefront key -----------
     int max_key = 0;
     for (auto& J : jobs)
-        for (int k : J.plan.key) max_key = std::max(max_key, k);
+        for (int k : J.plan->key) max_key = std::max(max_key, k);
     std::vector<int32_t> kcount(max_key + 2, 0);
     for (auto& J : jobs)
-        for (int k : J.plan.key) kcount[k + 1]++;
+        for (int k : J.plan->key) kcount[k + 1]++;
     for (int k = 0; k <= max_key; ++k) kcount[k + 1] += kcount[k];
     std::vector<int32_t> kstart(kcount.begin(), kcount.end());
     const int64_t ntk = stats.n_blocks;
     std::vector<int32_t> tickets(2 * std::max<int64_t>(ntk, 1));
     for (size_t j = 0; j < jobs.size(); ++j)
-        for (size_t b = 0; b < jobs[j].plan.key.size(); ++b) {
-            const int pos = kcount[jobs[j].plan.key[b]]++;
+        for (size_t b = 0; b < jobs[j].plan->key.size(); ++b) {
+            const int pos = kcount[jobs[j].plan->key[b]]++;
             tickets[2 * pos] = (int32_t)j;
             tickets[2 * pos + 1] = (int32_t)b;
         }
@@ -339,8 +345,8 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     size_t n_pix = 0, n_cells = 0, n_blk = 0;
     for (auto& J : jobs) {
         n_pix += (size_t)J.W * J.H;
-        n_cells += J.plan.owner.size();
-        n_blk += J.plan.desc.size() / 4;
+        n_cells += J.plan->owner.size();
+        n_blk += J.plan->desc.size() / 4;
     }
     if ((e = ws.recon.ensure(n_pix * sizeof(double))) != hipSuccess) return from_hip(e);
     if ((e = ws.status.ensure(n_pix)) != hipSuccess) return from_hip(e);
@@ -373,16 +379,16 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     std::vector<size_t> off_pix(jobs.size() + 1, 0), off_cell(jobs.size() + 1, 0), off_blk(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j) {
         off_pix[j + 1] = off_pix[j] + (size_t)jobs[j].W * jobs[j].H;
-        off_cell[j + 1] = off_cell[j] + jobs[j].plan.owner.size();
-        off_blk[j + 1] = off_blk[j] + jobs[j].plan.desc.size() / 4;
+        off_cell[j + 1] = off_cell[j] + jobs[j].plan->owner.size();
+        off_blk[j + 1] = off_blk[j] + jobs[j].plan->desc.size() / 4;
     }
     parallel_for(jobs.size(), [&](size_t j) {
         const HostJob& J = jobs[j];
-        const size_t nb = J.plan.desc.size() / 4;
+        const size_t nb = J.plan->desc.size() / 4;
         const size_t o_pix = off_pix[j], o_cell = off_cell[j], o_blk = off_blk[j];
-        std::copy(J.plan.owner.begin(), J.plan.owner.end(), h_owner + o_cell);
-        std::copy(J.plan.desc.begin(), J.plan.desc.end(), h_desc + 4 * o_blk);
-        std::copy(J.plan.lbox.begin(), J.plan.lbox.end(), h_lbox + 4 * o_blk);
+        std::copy(J.plan->owner.begin(), J.plan->owner.end(), h_owner + o_cell);
+        std::copy(J.plan->desc.begin(), J.plan->desc.end(), h_desc + 4 * o_blk);
+        std::copy(J.plan->lbox.begin(), J.plan->lbox.end(), h_lbox + 4 * o_blk);
         JobDev D{};
         D.img = images[J.img].data;
         D.mask = masks[J.img].data;
@@ -400,8 +406,8 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         D.cy0 = J.cy0;
         D.cx1 = J.cx1;
         D.cy1 = J.cy1;
-        D.fw = J.plan.fw;
-        D.fh = J.plan.fh;
+        D.fw = J.plan->fw;
+        D.fh = J.plan->fh;
         D.owner = (const int32_t*)ws.owner.p + o_cell;
         D.desc = (const int4*)ws.desc.p + o_blk;
         D.lbox = (const int4*)ws.lbox.p + o_blk;
@@ -464,7 +470,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         std::vector<int32_t> raster(2 * ntk);
         size_t q = 0;
         for (size_t j = 0; j < jobs.size(); ++j)
-            for (size_t b = 0; b < jobs[j].plan.key.size(); ++b) {
+            for (size_t b = 0; b < jobs[j].plan->key.size(); ++b) {
                 raster[2 * q] = (int32_t)j;
                 raster[2 * q + 1] = (int32_t)b;
                 ++q;

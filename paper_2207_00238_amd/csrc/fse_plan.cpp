@@ -8,6 +8,9 @@
 #include "fse_plan.h"
 
 #include <algorithm>
+#if defined(__SSE2__)
+#include <emmintrin.h>
+#endif
 
 namespace fse {
 
@@ -36,11 +39,84 @@ bool blocks_interact(const int32_t* di, const int32_t* li, const int32_t* dj, co
     return a || b;
 }
 
+// Lost-pixel bit set of one mask row: bit x%64 of word x/64 is set when
+// pixel x is lost.  Sixteen bytes at a time where SSE2 is there.
+static void row_bits(const uint8_t* row, int W, uint64_t* out) {
+    const int nw = (W + 63) / 64;
+    for (int w = 0; w < nw; ++w) out[w] = 0;
+    int x = 0;
+#if defined(__SSE2__)
+    const __m128i z = _mm_setzero_si128();
+    for (; x + 16 <= W; x += 16) {
+        const __m128i v = _mm_loadu_si128(reinterpret_cast<const __m128i*>(row + x));
+        const uint32_t zero = (uint32_t)_mm_movemask_epi8(_mm_cmpeq_epi8(v, z));
+        out[x >> 6] |= (uint64_t)(~zero & 0xFFFFu) << (x & 63);
+    }
+#endif
+    for (; x < W; ++x) out[x >> 6] |= (uint64_t)(row[x] != 0) << (x & 63);
+}
+
+namespace {
+
+struct CellStat {
+    uint16_t cnt;            // lost pixels in the cell
+    uint8_t y0, y1, x0, x1;  // their bounding box, cell-relative
+};
+
+// popcount of one byte without a CPU popcount instruction
+struct Popc8 {
+    uint8_t v[256];
+    constexpr Popc8() : v() {
+        for (int i = 0; i < 256; ++i) v[i] = (uint8_t)((i & 1) + ((i >> 1) & 1) + ((i >> 2) & 1) + ((i >> 3) & 1) +
+                                                       ((i >> 4) & 1) + ((i >> 5) & 1) + ((i >> 6) & 1) + (i >> 7));
+    }
+};
+constexpr Popc8 kPopc8;
+
+// Cell statistics of one row of fine cells from its BM mask rows (ny <= BM
+// rows at the bottom edge), given as bit sets of nw64 words each.  BM divides
+// 64, so a cell never straddles two words.  Cells without lost pixels are
+// skipped word by word.
+template <int BM>
+int64_t cell_row(const uint64_t* rb, int nw64, int ny, int fw, CellStat* crow) {
+    constexpr uint64_t CM = BM == 64 ? ~0ull : ((1ull << BM) - 1);
+    constexpr int PER = 64 / BM;  // cells per word
+    int64_t lost = 0;
+    for (int w = 0; w < nw64; ++w) {
+        uint64_t orw = 0;
+        for (int r = 0; r < ny; ++r) orw |= rb[(size_t)r * nw64 + w];
+        const int fx0 = w * PER, fx1 = std::min(fw, fx0 + PER);
+        for (int fx = fx0; fx < fx1; ++fx) crow[fx] = CellStat{0, 255, 0, 255, 0};
+        while (orw) {
+            const int k = __builtin_ctzll(orw) / BM;  // cell within the word
+            orw &= ~(CM << (k * BM));
+            const int fx = fx0 + k;
+            if (fx >= fw) break;
+            uint32_t any = 0;
+            int n = 0, y0 = 255, y1 = 0;
+            for (int r = 0; r < ny; ++r) {
+                const uint32_t bits = (uint32_t)((rb[(size_t)r * nw64 + w] >> (k * BM)) & CM);
+                any |= bits;
+                n += kPopc8.v[bits & 255] + kPopc8.v[(bits >> 8) & 255];
+                y0 = (bits && y0 == 255) ? r : y0;
+                y1 = bits ? r + 1 : y1;
+            }
+            crow[fx] = CellStat{(uint16_t)n, (uint8_t)y0, (uint8_t)y1, (uint8_t)__builtin_ctz(any),
+                                (uint8_t)(32 - __builtin_clz(any))};
+            lost += n;
+        }
+    }
+    return lost;
+}
+
+}  // namespace
+
 bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::vector<ClassCfg>& cls,
-                 RegionPlan& P) {
+                 RegionPlan& P, PlanScratch& S) {
     const int nc = (int)cls.size();
     if (nc < 1) return false;
     const int Bmin = cls.back().B;
+    if (Bmin != 1 && Bmin != 2 && Bmin != 4 && Bmin != 8 && Bmin != 16) return false;
     for (int c = 0; c + 1 < nc; ++c)
         if (cls[c].B % cls[c + 1].B != 0 || cls[c].B <= cls[c + 1].B) return false;
     P.W = W;
@@ -48,82 +124,107 @@ bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::ve
     P.fw = (W + Bmin - 1) / Bmin;
     P.fh = (H + Bmin - 1) / Bmin;
     const int fw = P.fw, fh = P.fh;
-    // per fine cell: any lost pixel, every pixel lost (cell fully inside)
-    std::vector<uint8_t> any(fw * (size_t)fh, 0), all(fw * (size_t)fh, 0);
+    const size_t ncell = fw * (size_t)fh;
+    // pass 1, row-major over the mask: per fine cell the number of lost
+    // pixels and their bounding box
+    S.cells.resize(ncell * sizeof(CellStat));
+    CellStat* cs = reinterpret_cast<CellStat*>(S.cells.data());
+    const int nw64 = (W + 63) / 64;
+    S.bits.resize((size_t)nw64 * Bmin);
+    uint64_t* rb = S.bits.data();
     int64_t lost = 0;
-    for (int fy = 0; fy < fh; ++fy)
-        for (int fx = 0; fx < fw; ++fx) {
-            const int y0 = fy * Bmin, x0 = fx * Bmin;
-            const int y1 = std::min(H, y0 + Bmin), x1 = std::min(W, x0 + Bmin);
-            int cnt = 0;
-            for (int y = y0; y < y1; ++y) {
-                const uint8_t* row = mask + (int64_t)y * pitch;
-                for (int x = x0; x < x1; ++x) cnt += row[x] != 0;
-            }
-            lost += cnt;
-            any[fy * (size_t)fw + fx] = cnt > 0;
-            all[fy * (size_t)fw + fx] = (cnt == Bmin * Bmin);
+    for (int fy = 0; fy < fh; ++fy) {
+        const int ny = std::min(Bmin, H - fy * Bmin);
+        for (int r = 0; r < ny; ++r) row_bits(mask + (int64_t)(fy * Bmin + r) * pitch, W, rb + (size_t)r * nw64);
+        CellStat* crow = cs + fy * (size_t)fw;
+        switch (Bmin) {
+            case 1: lost += cell_row<1>(rb, nw64, ny, fw, crow); break;
+            case 2: lost += cell_row<2>(rb, nw64, ny, fw, crow); break;
+            case 4: lost += cell_row<4>(rb, nw64, ny, fw, crow); break;
+            case 8: lost += cell_row<8>(rb, nw64, ny, fw, crow); break;
+            default: lost += cell_row<16>(rb, nw64, ny, fw, crow); break;
         }
+    }
     P.lost_pixels = lost;
-    // class of every fine cell: first (largest) class whose aligned square is
-    // entirely lost and inside the region, else the last class if any lost
-    std::vector<int8_t> ccls(fw * (size_t)fh, -1);
+    // pass 2: class of every fine cell -- the first (largest) class whose
+    // aligned square is entirely lost and inside the region, else the last
+    // class if any pixel is lost -- and the number of blocks (corner cells)
+    const int full_cnt = Bmin * Bmin;
+    S.ccls.resize(ncell);
+    int8_t* ccls = S.ccls.data();
+    size_t nblk = 0;
     for (int fy = 0; fy < fh; ++fy)
         for (int fx = 0; fx < fw; ++fx) {
+            const size_t q = fy * (size_t)fw + fx;
             int8_t got = -1;
-            for (int c = 0; c + 1 < nc && got < 0; ++c) {
-                const int f = cls[c].B / Bmin;
-                const int cy = fy / f * f, cx = fx / f * f;
-                if ((cy + f) * Bmin > H || (cx + f) * Bmin > W) continue;
-                bool full = true;
-                for (int yy = cy; yy < cy + f && full; ++yy)
-                    for (int xx = cx; xx < cx + f; ++xx)
-                        if (!all[yy * (size_t)fw + xx]) {
-                            full = false;
-                            break;
-                        }
-                if (full) got = (int8_t)c;
+            if (cs[q].cnt) {
+                for (int c = 0; c + 1 < nc && got < 0; ++c) {
+                    const int f = cls[c].B / Bmin;
+                    const int cy = fy / f * f, cx = fx / f * f;
+                    if ((cy + f) * Bmin > H || (cx + f) * Bmin > W) continue;
+                    bool full = true;
+                    for (int yy = cy; yy < cy + f && full; ++yy)
+                        for (int xx = cx; xx < cx + f; ++xx)
+                            if (cs[yy * (size_t)fw + xx].cnt != full_cnt) {
+                                full = false;
+                                break;
+                            }
+                    if (full) got = (int8_t)c;
+                }
+                if (got < 0) got = (int8_t)(nc - 1);
+                const int f = cls[got].B / Bmin;
+                nblk += (fy % f == 0 && fx % f == 0);
             }
-            if (got < 0 && any[fy * (size_t)fw + fx]) got = (int8_t)(nc - 1);
-            ccls[fy * (size_t)fw + fx] = got;
+            ccls[q] = got;
         }
-    // blocks: corner cells in raster order of the fine grid
-    P.owner.assign(fw * (size_t)fh, -1);
-    P.desc.clear();
-    P.lbox.clear();
-    P.key.clear();
+    // pass 3: blocks at corner cells in raster order of the fine grid, and
+    // the owner of every cell (a square's corner comes first in raster order)
+    P.owner.resize(ncell);
+    P.desc.resize(4 * nblk);
+    P.lbox.resize(4 * nblk);
+    P.key.resize(nblk);
     const int D = key_reach_cells(cls);
-    std::vector<int32_t> corner_id(fw * (size_t)fh, -1);
+    S.corner.resize(ncell);
+    int32_t* corner_id = S.corner.data();
+    int32_t* owner = P.owner.data();
+    size_t id = 0;
     for (int fy = 0; fy < fh; ++fy)
         for (int fx = 0; fx < fw; ++fx) {
-            const int c = ccls[fy * (size_t)fw + fx];
-            if (c < 0) continue;
+            const size_t q = fy * (size_t)fw + fx;
+            const int c = ccls[q];
+            if (c < 0) {
+                owner[q] = -1;
+                continue;
+            }
             const int f = cls[c].B / Bmin;
-            if (fy % f || fx % f) continue;
-            const int id = (int)(P.desc.size() / 4);
-            corner_id[fy * (size_t)fw + fx] = id;
+            if (fy % f || fx % f) {
+                owner[q] = corner_id[(fy / f * f) * (size_t)fw + (fx / f * f)];
+                continue;
+            }
+            corner_id[q] = (int32_t)id;
+            owner[q] = (int32_t)id;
             const int y0 = fy * Bmin, x0 = fx * Bmin;
-            P.desc.insert(P.desc.end(), {y0, x0, c, 0});
-            // bounding box of the lost pixels
-            int ly0 = H, lx0 = W, ly1 = -1, lx1 = -1;
-            const int B = cls[c].B;
-            for (int y = y0; y < std::min(H, y0 + B); ++y)
-                for (int x = x0; x < std::min(W, x0 + B); ++x)
-                    if (mask[(int64_t)y * pitch + x]) {
-                        ly0 = std::min(ly0, y);
-                        lx0 = std::min(lx0, x);
-                        ly1 = std::max(ly1, y);
-                        lx1 = std::max(lx1, x);
-                    }
-            P.lbox.insert(P.lbox.end(), {ly0, lx0, ly1 + 1, lx1 + 1});
-            P.key.push_back(fx + (D + 1) * fy);
-        }
-    for (int fy = 0; fy < fh; ++fy)
-        for (int fx = 0; fx < fw; ++fx) {
-            const int c = ccls[fy * (size_t)fw + fx];
-            if (c < 0) continue;
-            const int f = cls[c].B / Bmin;
-            P.owner[fy * (size_t)fw + fx] = corner_id[(fy / f * f) * (size_t)fw + (fx / f * f)];
+            int32_t* dd = &P.desc[4 * id];
+            dd[0] = y0;
+            dd[1] = x0;
+            dd[2] = c;
+            dd[3] = 0;
+            // bounding box of the lost pixels: a larger class owns a fully lost
+            // square; the smallest class owns one cell
+            int32_t* lb = &P.lbox[4 * id];
+            if (c + 1 < nc) {
+                lb[0] = y0;
+                lb[1] = x0;
+                lb[2] = y0 + cls[c].B;
+                lb[3] = x0 + cls[c].B;
+            } else {
+                lb[0] = y0 + cs[q].y0;
+                lb[1] = x0 + cs[q].x0;
+                lb[2] = y0 + cs[q].y1;
+                lb[3] = x0 + cs[q].x1;
+            }
+            P.key[id] = fx + (D + 1) * fy;
+            ++id;
         }
     return true;
 }

@@ -23,12 +23,21 @@ struct RegionPlan {
     int64_t lost_pixels = 0;
 };
 
+// Working storage of plan_region, kept by the caller between calls so that
+// repeated planning reuses its memory.
+struct PlanScratch {
+    std::vector<uint8_t> cells;   // per fine cell: lost count and box (packed)
+    std::vector<int8_t> ccls;     // per fine cell: class, -1 none
+    std::vector<int32_t> corner;  // per fine cell: block id of a corner cell
+    std::vector<uint64_t> bits;   // Bmin mask rows as bit sets
+};
+
 // Block geometry shared by the planner and the kernels: the largest class
 // whose aligned square is entirely lost (and inside the region) takes it;
 // the smallest class takes every remaining cell holding a lost pixel.
 // mask: region view (row pitch in elements).  Returns false on bad classes.
 bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::vector<ClassCfg>& cls,
-                 RegionPlan& out);
+                 RegionPlan& out, PlanScratch& scratch);
 
 // Key slope: a block can only interact with blocks whose corner lies at most
 // D fine cells to its right in an earlier row, so key = cx + (D + 1) cy

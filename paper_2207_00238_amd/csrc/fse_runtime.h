@@ -4,11 +4,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <deque>
 #include <mutex>
 #include <vector>
 
 #include "../../include/fse.h"
 #include "fse_internal.h"
+#include "fse_plan.h"
 
 namespace fse {
 
@@ -33,6 +35,9 @@ struct Workspace {
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the block kernel(s) of the last call
     bool timed = false;
+    // host planning state per job, reused between calls
+    std::deque<RegionPlan> plans;
+    std::vector<PlanScratch> plan_scratch;
     void free_all();
 };
 

@@ -22,8 +22,8 @@
  *    pitch counted in elements.  Values of the input at lost pixels are never
  *    read (they may be NaN).  The output receives the input at known pixels
  *    and the extrapolated value at lost pixels; it must not alias the input.
- *  - The library owns its device workspace (planning tables, per-pixel
- *    status, an FP64 copy of reconstructed values, scheduling counters).  It
+ *  - The library owns its device workspace (planning tables, a per-pixel
+ *    FP64 copy of reconstructed values, scheduling counters).  It
  *    grows on demand and is kept per stream until fse_release() or exit.
  *  - A fault of the device surfaces as FSE_ERR_DEVICE on the call that
  *    observes it.

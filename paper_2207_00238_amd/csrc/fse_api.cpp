@@ -86,7 +86,7 @@ void release_all_workspaces() {
 }
 
 void Workspace::free_all() {
-    for (DevBuf* b : {&recon, &status, &owner, &desc, &lbox, &done, &tickets, &jobs, &misc, &tabs}) b->release();
+    for (DevBuf* b : {&recon, &owner, &desc, &lbox, &done, &tickets, &jobs, &misc, &tabs}) b->release();
     tab_key.clear();
     if (host_mask) hipHostFree(host_mask);
     if (stage) hipHostFree(stage);
@@ -303,6 +303,8 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
             }
         }
     }
+    int reach = 0;  // largest support border: the reach of the kernel's dependency scan
+    for (auto& c : cls) reach = std::max(reach, c.b);
     // plans and planning scratch live in the workspace (memory reused)
     while (ws.plans.size() < jobs.size()) ws.plans.emplace_back();
     if (ws.plan_scratch.size() < jobs.size()) ws.plan_scratch.resize(jobs.size());
@@ -312,6 +314,8 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         HostJob& J = jobs[j];
         const uint8_t* mk = ws.host_mask + moff[J.img] + (size_t)J.oy * images[J.img].width + J.ox;
         plan_ok[j] = plan_region(mk, images[J.img].width, J.W, J.H, cls, *J.plan, ws.plan_scratch[j]);
+        if (plan_ok[j] && p->schedule == FSE_SCHED_PERSISTENT)
+            plan_levels(*J.plan, cls, reach, ws.plan_scratch[j].cell_level);
     });
     for (size_t j = 0; j < jobs.size(); ++j) {
         if (!plan_ok[j]) return FSE_ERR_INVALID_ARG;
@@ -340,6 +344,27 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     int nkeys = 0;
     for (int k = 0; k <= max_key; ++k) nkeys += kstart[k + 1] > kstart[k];
     stats.wavefront_keys = nkeys;
+    // persistent schedule: stable re-sort of the key order by dependency level,
+    // (level, key) -- still a topological order; ready blocks come first
+    int n_levels = nkeys;
+    if (p->schedule == FSE_SCHED_PERSISTENT && ntk > 0) {
+        int max_lv = 0;
+        for (auto& J : jobs)
+            for (int l : J.plan->level) max_lv = std::max(max_lv, l);
+        std::vector<int32_t> lcount(max_lv + 2, 0);
+        for (auto& J : jobs)
+            for (int l : J.plan->level) lcount[l + 1]++;
+        for (int l = 0; l <= max_lv; ++l) lcount[l + 1] += lcount[l];
+        std::vector<int32_t> by_level(tickets.size());
+        for (int64_t q = 0; q < ntk; ++q) {
+            const int j = tickets[2 * q], b = tickets[2 * q + 1];
+            const int pos = lcount[jobs[j].plan->level[b]]++;
+            by_level[2 * pos] = j;
+            by_level[2 * pos + 1] = b;
+        }
+        tickets.swap(by_level);
+        n_levels = max_lv + 1;
+    }
 
     // ---- device buffers -----------------------------------------------------
     size_t n_pix = 0, n_cells = 0, n_blk = 0;
@@ -349,7 +374,6 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         n_blk += J.plan->desc.size() / 4;
     }
     if ((e = ws.recon.ensure(n_pix * sizeof(double))) != hipSuccess) return from_hip(e);
-    if ((e = ws.status.ensure(n_pix)) != hipSuccess) return from_hip(e);
     if ((e = ws.owner.ensure(std::max<size_t>(n_cells, 1) * 4)) != hipSuccess) return from_hip(e);
     if ((e = ws.desc.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
     if ((e = ws.lbox.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
@@ -397,7 +421,6 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         D.mask_pitch = masks[J.img].pitch;
         D.out_pitch = outs[J.img].pitch;
         D.recon = (double*)ws.recon.p + o_pix;
-        D.status = (uint8_t*)ws.status.p + o_pix;
         D.W = J.W;
         D.H = J.H;
         D.ox = J.ox;
@@ -437,8 +460,6 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     a.error = misc;
     a.degenerate = (int64_t*)(misc + 2);
     a.Bmin = cls.back().B;
-    int reach = 0;
-    for (auto& c : cls) reach = std::max(reach, c.b);
     a.reach = reach;
     a.gamma = p->gamma;
     a.delta = p->recon_weight;
@@ -454,13 +475,14 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     bool wide = false;
     for (auto& c : cls) wide |= (c.M == 64);
     const int nw = wide ? 4 : (p->block_waves > 0 ? p->block_waves : 4);
-    // Automatic grid: about twice the average number of blocks that share a
-    // wavefront key.  A dependency chain runs fastest when its blocks do not
+    // Automatic grid: about twice the average number of blocks per dependency
+    // level (per wavefront key for the other schedules).  A dependency chain
+    // runs fastest when its blocks do not
     // share SIMDs with blocks that cannot start yet, so a grid much larger than
     // the available parallelism only slows the chain.
     int grid = p->workgroups;
     if (grid <= 0) {
-        const int64_t par = (ntk + std::max(1, nkeys) - 1) / std::max(1, nkeys);
+        const int64_t par = (ntk + std::max(1, n_levels) - 1) / std::max(1, n_levels);
         const int64_t want = std::max<int64_t>(64, ((2 * par + 63) / 64) * 64);
         grid = (int)std::min<int64_t>(want, persistent_grid(nw, p->precision, wide));
     }

@@ -10,9 +10,6 @@ namespace fse {
 constexpr int kMaxThreads = 256;  // one processing block per workgroup of 1, 2 or 4 wave64
 constexpr int kMaxClasses = 3;
 
-// Pixel status inside a job's working state.
-enum : uint8_t { kKnown = 0, kLost = 1, kRecon = 2 };
-
 struct ClassDev {
     int32_t B, b, M, K;
     const double* wtab;  // M*M: rho^dist from the window centre (FP64)
@@ -25,8 +22,7 @@ struct JobDev {
     const uint8_t* mask;  // source mask
     float* out;           // destination image (full-image coordinates)
     int64_t img_pitch, mask_pitch, out_pitch;
-    double* recon;    // region W*H: FP64 reconstructed values
-    uint8_t* status;  // region W*H
+    double* recon;    // region W*H: FP64 reconstructed values (valid where written)
     int32_t W, H;     // region size
     int32_t ox, oy;   // region origin in the source image
     int32_t cx0, cy0, cx1, cy1;  // core rectangle (region coords); output written only inside

@@ -46,7 +46,6 @@ __global__ void k_init_job(const JobDev* __restrict__ jobs, int32_t* counter, in
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < J.W; x += gridDim.x * blockDim.x) {
         const int gy = J.oy + y, gx = J.ox + x;
         const uint8_t lost = J.mask[(int64_t)gy * J.mask_pitch + gx] != 0;
-        J.status[(int64_t)y * J.W + x] = lost ? kLost : kKnown;
         if (!lost && y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
             J.out[(int64_t)gy * J.out_pitch + gx] = J.img[(int64_t)gy * J.img_pitch + gx];
     }
@@ -93,14 +92,15 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
     return ay0 < by1 && by0 < ay1 && ax0 < bx1 && bx0 < ax1;
 }
 
-// LDS layout.  One area holds, in turn: the DFT operands X (w*s and w, M x
-// (M+1) each); the weight spectrum during the K steps (M = 32: 64 x 32
-// complex with duplicated rows; M = 64: 64 x 64 complex); the coefficient list
-// for the synthesis.  Sized for M = 32 (32 KB) or, when a launch has M = 64
-// blocks, for M = 64 (65 KB).
+// LDS layout.  The area holds w*s (M x (M+1)), kept from before the
+// dependency wait until the DFT of w*s after it, followed by a region that
+// first holds w (M x (M+1)) and then the weight spectrum for the K steps
+// (M = 32: 64 x 32 complex with duplicated rows; M = 64: 64 x 64 complex).
+// The coefficient list lives in the head.  Sized for M = 32 (41 KB) or, when a
+// launch has M = 64 blocks, for M = 64 (97 KB).
 constexpr int kMaxK = 256;
-constexpr int kBufDoubles32 = 4096;
-constexpr int kBufDoubles64 = 2 * 64 * 65;
+constexpr int kBufDoubles32 = 32 * 33 + 2 * 32 * 32 * 2;  // w*s, then the duplicated weight spectrum
+constexpr int kBufDoubles64 = 64 * 65 + 64 * 64 * 2;      // w*s, then the weight spectrum
 
 struct SharedHead {
     double twc32[32], tws32[32];
@@ -307,6 +307,9 @@ struct TileMap {
     }
 };
 
+template <int NT>
+__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S);
+
 template <int M, int NW, int PREC>
 __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& H, double* buf) {
     using T = typename PrecType<PREC>::T;
@@ -336,9 +339,17 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
 
     // ---- stage the window: weights and weighted values --------------------
+    // A window pixel is known (weight rho^dist), lost and owned by an earlier
+    // block (reconstructed by the time this block runs in raster order:
+    // delta rho^dist), or lost otherwise (0) -- fixed by the mask and the plan,
+    // so the weights, W0, the known part of w*s and the weight spectrum are
+    // formed before the dependency wait; only the reconstructed values wait.
     T* Xs = reinterpret_cast<T*>(buf);  // w * s, [m][n] stride LD
-    T* Xw = Xs + M * LD;                // w
+    T* Wd = Xs + M * LD;                // weight spectrum [DUP ? 2M : M][M] complex
+    T* Xw = Wd;                         // w, staged where the weight spectrum goes
+    const int Bm = a.Bmin;
     double wsum = 0.0;
+    unsigned recon_bits = 0;  // this thread's pixels that hold reconstructed values
 #pragma unroll
     for (int j = 0; j < NPIX; ++j) {
         const int m = (t >> LOGM) + RS * j, n = t & MASK;
@@ -346,21 +357,20 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         double w = 0.0, v = 0.0;
         bool lost = false;
         if (y >= 0 && y < J.H && x >= 0 && x < J.W) {
-            // all four loads in flight together; the status picks afterwards
-            const int64_t q = (int64_t)y * J.W + x;
-            const uint8_t st = J.status[q];
+            // independent loads, in flight together
+            lost = J.mask[(int64_t)(J.oy + y) * J.mask_pitch + (J.ox + x)] != 0;
+            const int own = J.owner[(y / Bm) * J.fw + x / Bm];
             const double wt = C.wtab[m * M + n];
             const double sv = (double)J.img[(int64_t)(J.oy + y) * J.img_pitch + (J.ox + x)];
-            const double rv = J.recon[q];
-            w = st == kKnown ? wt : (st == kRecon ? a.delta * wt : 0.0);
-            v = st == kKnown ? sv : (st == kRecon ? rv : 0.0);
-            lost = st == kLost;
+            const bool rec = lost && own < blk;
+            w = !lost ? wt : (rec ? a.delta * wt : 0.0);
+            v = !lost ? sv : 0.0;
+            recon_bits |= (unsigned)rec << j;
         }
         Xs[m * LD + n] = (T)(w * v);
         Xw[m * LD + n] = (T)w;
         wsum += w;
-        // lost pixels of the core, synthesised at the end (only this block
-        // writes them, so the status cannot change in between)
+        // lost pixels of the core, synthesised at the end
         if (m >= b && m < b + B && n >= b && n < b + B) H.lost[(m - b) * B + (n - b)] = lost;
     }
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
@@ -370,12 +380,15 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 #pragma unroll
     for (int q = 1; q < NW; ++q) W0 += H.part[q];
 
-    // ---- stage 1: T(:, tj) = X F(:, tj), both inputs ------------------------
-    // F = C - i S with C[k,m] = cos(2 pi k m / M), S[k,m] = sin(2 pi k m / M)
+    // ---- DFT of one input (1: w -> weight spectrum in LDS, 0: w*s -> R in
+    // registers) as F X F in two stages of MFMA GEMMs
+    // stage 1: T(:, tj) = X F(:, tj); F = C - i S with C[k,m] = cos(2 pi k m / M),
+    // S[k,m] = sin(2 pi k m / M)
     const int li = lane & 15, lk = lane >> 4;
-    acc4 t1[2][NTJ][TM::TL][2];  // [input][column tile][row tile][re, im]
-#pragma unroll
-    for (int inp = 0; inp < 2; ++inp) {
+    T rr[EPT], ri[EPT];
+    auto dft = [&](const int inp) {
+    acc4 t1[NTJ][TM::TL][2];  // [column tile][row tile][re, im]
+    {
         const T* X = inp ? Xw : Xs;
 #pragma unroll
         for (int cj = 0; cj < NTJ; ++cj) {
@@ -407,19 +420,16 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                         ci = mfma_step(av, (T)(-tws[p]), ci);
                     }
                 }
-                t1[inp][cj][ti][0] = cr;
-                t1[inp][cj][ti][1] = ci;
+                t1[cj][ti][0] = cr;
+                t1[cj][ti][1] = ci;
             }
         }
     }
-    __syncthreads();  // X is dead; the weight spectrum takes its place
+    if (inp == 1) __syncthreads();  // w is dead; the weight spectrum takes its place
 
-    // ---- stage 2: F T for the wave's tiles ----------------------------------
-    // (F T)_re = C T_re + S T_im,  (F T)_im = C T_im - S T_re
-    T* Wd = reinterpret_cast<T*>(buf);  // weight spectrum [DUP ? 2M : M][M] complex
-    T rr[EPT], ri[EPT];
-#pragma unroll
-    for (int inp = 1; inp >= 0; --inp) {
+    // stage 2: F T for the wave's tiles; (F T)_re = C T_re + S T_im,
+    // (F T)_im = C T_im - S T_re
+    {
 #pragma unroll
         for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
@@ -437,8 +447,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                             c[q] = (float)twc[p];
                             sn[q] = (float)tws[p];
                             nsn[q] = -sn[q];
-                            bre[q] = t1[inp][cj][kk][0][q];
-                            bim[q] = t1[inp][cj][kk][1][q];
+                            bre[q] = t1[cj][kk][0][q];
+                            bim[q] = t1[cj][kk][1][q];
                         }
                         ore = mfma_step3(c, bre, ore);
                         ore = mfma_step3(sn, bim, ore);
@@ -452,8 +462,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                         const int k = F64 ? (kk * 4 + lk) : ((kk >> 2) * 16 + 4 * lk + (kk & 3));
                         const int p = ((ti_o * 16 + li) * k) & MASK;
                         const T c = (T)twc[p], sn = (T)tws[p];
-                        const T bre = t1[inp][cj][kk >> 2][0][kk & 3];
-                        const T bim = t1[inp][cj][kk >> 2][1][kk & 3];
+                        const T bre = t1[cj][kk >> 2][0][kk & 3];
+                        const T bim = t1[cj][kk >> 2][1][kk & 3];
                         ore = mfma_step(c, bre, ore);
                         ore = mfma_step(sn, bim, ore);
                         oim = mfma_step(c, bim, oim);
@@ -480,6 +490,23 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             }
         }
     }
+    };
+
+    dft(1);  // weight spectrum, before the wait
+
+    // ---- wait for the earlier blocks this block depends on, then add their
+    // reconstructed values to w*s
+    wait_predecessors<NT>(a, J, blk, H);
+#pragma unroll
+    for (int j = 0; j < NPIX; ++j) {
+        if (recon_bits >> j & 1) {
+            const int m = (t >> LOGM) + RS * j, n = t & MASK;
+            const int64_t q = (int64_t)(wy + m) * J.W + (wx + n);
+            Xs[m * LD + n] = (T)(a.delta * C.wtab[m * M + n] * J.recon[q]);
+        }
+    }
+    __syncthreads();
+    dft(0);  // R
     __syncthreads();
 
     // ---- K greedy steps ----------------------------------------------------
@@ -622,7 +649,6 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             const int y = d.x + py, x = d.y + pxx;
             const int64_t q = (int64_t)y * J.W + x;
             J.recon[q] = val;
-            J.status[q] = kRecon;
             if (y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
                 J.out[(int64_t)(J.oy + y) * J.out_pitch + (J.ox + x)] = (float)val;
         }
@@ -729,7 +755,6 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blo
         const int job = __builtin_amdgcn_readfirstlane(H.job), blk = __builtin_amdgcn_readfirstlane(H.blk);
         if (job < 0) break;
         const JobDev J = const_load(a.jobs + job);
-        wait_predecessors<64 * NW>(a, J, blk, H);
         if constexpr (WIDE) {
             if (a.cls[J.desc[blk].z].M == 64)
                 process_block<64, NW, PREC>(a, J, blk, H, buf);

@@ -229,6 +229,39 @@ bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::ve
     return true;
 }
 
+void plan_levels(RegionPlan& P, const std::vector<ClassCfg>& cls, int reach, std::vector<int32_t>& cell_level) {
+    // Levels over a superset of the kernel's waits: every earlier block owning
+    // a fine cell in the rows of the kernel's scan up to the block's own corner
+    // row (every earlier block the kernel's scan finds owns such a cell).  A
+    // superset of the edges still orders every real wait, and needs no box
+    // tests: a running maximum over the cells, each cell holding the level of
+    // its owner once that block has been assigned one (-1 before).
+    const size_t nb = P.key.size();
+    P.level.resize(nb);
+    const int Bmin = cls.back().B;
+    const int fw = P.fw;
+    cell_level.assign(P.owner.size(), -1);
+    for (size_t j = 0; j < nb; ++j) {
+        const int32_t* dj = &P.desc[4 * j];
+        const int Bj = cls[dj[2]].B;
+        const int ry0 = dj[0] - reach, rx0 = dj[1] - reach;
+        const int rx1 = dj[1] + Bj + reach;
+        const int fy0 = std::max(0, ry0 >= 0 ? ry0 / Bmin : 0), fx0 = std::max(0, rx0 >= 0 ? rx0 / Bmin : 0);
+        const int fx1 = std::min(fw - 1, (rx1 - 1) / Bmin);
+        const int fyj = dj[0] / Bmin, fxj = dj[1] / Bmin;
+        int m = -1;
+        for (int fy = fy0; fy <= fyj; ++fy) {
+            const int32_t* row = &cell_level[(size_t)fy * fw];
+            for (int fx = fx0; fx <= fx1; ++fx) m = std::max(m, row[fx]);
+        }
+        const int lv = m + 1;
+        P.level[j] = lv;
+        const int f = Bj / Bmin;
+        for (int fy = fyj; fy < std::min(P.fh, fyj + f); ++fy)
+            for (int fx = fxj; fx < std::min(fw, fxj + f); ++fx) cell_level[(size_t)fy * fw + fx] = lv;
+    }
+}
+
 bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
     xywh.clear();
     if (W < 1 || H < 1 || N < 1) return false;

@@ -20,6 +20,7 @@ struct RegionPlan {
     std::vector<int32_t> desc;   // 4 per block: y0, x0, class, 0 (raster order)
     std::vector<int32_t> lbox;   // 4 per block: lost-pixel bounding box y0, x0, y1, x1 (exclusive)
     std::vector<int32_t> key;    // wavefront key per block (a topological order of the dependencies)
+    std::vector<int32_t> level;  // longest dependency chain ending at the block (0 = no predecessor)
     int64_t lost_pixels = 0;
 };
 
@@ -30,6 +31,7 @@ struct PlanScratch {
     std::vector<int8_t> ccls;     // per fine cell: class, -1 none
     std::vector<int32_t> corner;  // per fine cell: block id of a corner cell
     std::vector<uint64_t> bits;   // Bmin mask rows as bit sets
+    std::vector<int32_t> cell_level;  // plan_levels: level of each cell's owner
 };
 
 // Block geometry shared by the planner and the kernels: the largest class
@@ -38,6 +40,13 @@ struct PlanScratch {
 // mask: region view (row pitch in elements).  Returns false on bad classes.
 bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::vector<ClassCfg>& cls,
                  RegionPlan& out, PlanScratch& scratch);
+
+// Dependency level of every block of P (P.level): 1 + the largest level of
+// the earlier blocks near it, over a superset of the waits of the block kernel
+// (so any order by level still runs every wait on an earlier block).  Sorting
+// by level keeps ready blocks ahead of blocks deep in a chain.  cell_level:
+// scratch, resized here.
+void plan_levels(RegionPlan& P, const std::vector<ClassCfg>& cls, int reach, std::vector<int32_t>& stamp);
 
 // Key slope: a block can only interact with blocks whose corner lies at most
 // D fine cells to its right in an earlier row, so key = cx + (D + 1) cy

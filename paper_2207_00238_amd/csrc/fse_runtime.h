@@ -26,7 +26,7 @@ struct DevBuf {
 // same stream share one workspace and are serialised by its mutex.
 struct Workspace {
     std::mutex mu;
-    DevBuf recon, status, owner, desc, lbox, done, tickets, jobs, misc, tabs;
+    DevBuf recon, owner, desc, lbox, done, tickets, jobs, misc, tabs;
     std::vector<double> tab_key;  // parameters the uploaded tables were built for
     uint8_t* host_mask = nullptr;  // pinned staging for mask read-back
     size_t host_mask_cap = 0;

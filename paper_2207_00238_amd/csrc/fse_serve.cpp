@@ -74,8 +74,8 @@ struct fse_server {
 namespace fse {
 
 // Device memory one request needs beyond its caller-owned buffers: FP64
-// reconstructed values and status per pixel, the fine-cell owner map, block
-// tables, tickets and flags (upper bounds).
+// reconstructed values per pixel, the fine-cell owner map, block tables,
+// tickets and flags (upper bounds).
 static int64_t request_bytes(const fse_image_t& im, const fse_params_t& p) {
     const int64_t px = (int64_t)im.width * im.height;
     int bmin = p.classes[p.n_classes - 1].block;
@@ -83,7 +83,7 @@ static int64_t request_bytes(const fse_image_t& im, const fse_params_t& p) {
     const int64_t cells = ((int64_t)im.width + bmin - 1) / bmin * (((int64_t)im.height + bmin - 1) / bmin);
     int64_t tiles_extra = 0;
     if (p.tiling == FSE_TILED) tiles_extra = px;  // overlap stripes, generous
-    return (px + tiles_extra) * 9 + cells * (4 + 16 + 16 + 4 + 8);
+    return (px + tiles_extra) * 8 + cells * (4 + 16 + 16 + 4 + 8);
 }
 
 // Requests can share a launch when every field that the kernels read agrees.

@@ -324,47 +324,51 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     for (auto& J : jobs) stats.n_lost_pixels += J.plan->lost_pixels;
     stats.n_jobs = (int64_t)jobs.size();
 
-    // ---- tickets: all blocks of all jobs ordered by wavefront key -----------
-    int max_key = 0;
-    for (auto& J : jobs)
-        for (int k : J.plan->key) max_key = std::max(max_key, k);
-    std::vector<int32_t> kcount(max_key + 2, 0);
-    for (auto& J : jobs)
-        for (int k : J.plan->key) kcount[k + 1]++;
-    for (int k = 0; k <= max_key; ++k) kcount[k + 1] += kcount[k];
-    std::vector<int32_t> kstart(kcount.begin(), kcount.end());
+    // ---- ticket order: a counting sort of all blocks of all jobs -------------
+    // The persistent schedule orders by dependency level (a topological order
+    // that keeps ready blocks ahead of blocks deep in a chain); the other
+    // schedules by wavefront key (the wavefront schedule launches one key at a
+    // time).  Within a bucket: job, then raster order.  Per-job histograms and
+    // the placement run in parallel; the tickets go straight into the pinned
+    // staging buffer below.
+    const bool by_level = p->schedule == FSE_SCHED_PERSISTENT;
     const int64_t ntk = stats.n_blocks;
-    std::vector<int32_t> tickets(2 * std::max<int64_t>(ntk, 1));
-    for (size_t j = 0; j < jobs.size(); ++j)
-        for (size_t b = 0; b < jobs[j].plan->key.size(); ++b) {
-            const int pos = kcount[jobs[j].plan->key[b]]++;
-            tickets[2 * pos] = (int32_t)j;
-            tickets[2 * pos + 1] = (int32_t)b;
-        }
+    const size_t nj = jobs.size();
+    auto sort_key = [&](size_t j) -> const std::vector<int32_t>& {
+        return by_level ? jobs[j].plan->level : jobs[j].plan->key;
+    };
+    std::vector<int32_t> job_max(nj, 0);
+    parallel_for(nj, [&](size_t j) {
+        int m = 0;
+        for (int k : sort_key(j)) m = std::max(m, k);
+        job_max[j] = m;
+    });
+    int max_key = 0;
+    for (int m : job_max) max_key = std::max(max_key, m);
+    const size_t nb_keys = (size_t)max_key + 1;
+    std::vector<int32_t> off(nj * nb_keys, 0);  // per job: histogram, then bucket offsets
+    parallel_for(nj, [&](size_t j) {
+        int32_t* h = &off[j * nb_keys];
+        for (int k : sort_key(j)) h[k]++;
+    });
+    std::vector<int32_t> kstart(nb_keys + 1, 0);
     int nkeys = 0;
-    for (int k = 0; k <= max_key; ++k) nkeys += kstart[k + 1] > kstart[k];
-    stats.wavefront_keys = nkeys;
-    // persistent schedule: stable re-sort of the key order by dependency level,
-    // (level, key) -- still a topological order; ready blocks come first
-    int n_levels = nkeys;
-    if (p->schedule == FSE_SCHED_PERSISTENT && ntk > 0) {
-        int max_lv = 0;
-        for (auto& J : jobs)
-            for (int l : J.plan->level) max_lv = std::max(max_lv, l);
-        std::vector<int32_t> lcount(max_lv + 2, 0);
-        for (auto& J : jobs)
-            for (int l : J.plan->level) lcount[l + 1]++;
-        for (int l = 0; l <= max_lv; ++l) lcount[l + 1] += lcount[l];
-        std::vector<int32_t> by_level(tickets.size());
-        for (int64_t q = 0; q < ntk; ++q) {
-            const int j = tickets[2 * q], b = tickets[2 * q + 1];
-            const int pos = lcount[jobs[j].plan->level[b]]++;
-            by_level[2 * pos] = j;
-            by_level[2 * pos + 1] = b;
+    {
+        int64_t run = 0;
+        for (size_t k = 0; k < nb_keys; ++k) {
+            kstart[k] = (int32_t)run;
+            const int64_t before = run;
+            for (size_t j = 0; j < nj; ++j) {
+                const int32_t c = off[j * nb_keys + k];
+                off[j * nb_keys + k] = (int32_t)run;
+                run += c;
+            }
+            nkeys += run > before;
         }
-        tickets.swap(by_level);
-        n_levels = max_lv + 1;
+        kstart[nb_keys] = (int32_t)run;
     }
+    stats.wavefront_keys = nkeys;  // distinct levels (persistent) or keys (other schedules)
+    const int n_levels = nkeys;
 
     // ---- device buffers -----------------------------------------------------
     size_t n_pix = 0, n_cells = 0, n_blk = 0;
@@ -378,7 +382,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     if ((e = ws.desc.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
     if ((e = ws.lbox.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
     if ((e = ws.done.ensure(std::max<size_t>(n_blk, 1) * 4)) != hipSuccess) return from_hip(e);
-    if ((e = ws.tickets.ensure(tickets.size() * 4)) != hipSuccess) return from_hip(e);
+    if ((e = ws.tickets.ensure((size_t)std::max<int64_t>(ntk, 1) * 8)) != hipSuccess) return from_hip(e);
     if ((e = ws.jobs.ensure(jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
     if ((e = ws.misc.ensure(64)) != hipSuccess) return from_hip(e);
 
@@ -399,7 +403,18 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     int32_t* h_desc = (int32_t*)(ws.stage + o_desc);
     int32_t* h_lbox = (int32_t*)(ws.stage + o_lbox);
     JobDev* h_jobs = (JobDev*)(ws.stage + o_jobs);
-    std::memcpy(ws.stage + o_tk, tickets.data(), (size_t)ntk * 8);
+    {
+        int32_t* tk = (int32_t*)(ws.stage + o_tk);
+        parallel_for(nj, [&](size_t j) {
+            int32_t* o = &off[j * nb_keys];
+            const std::vector<int32_t>& sk = sort_key(j);
+            for (size_t b = 0; b < sk.size(); ++b) {
+                const int32_t pos = o[sk[b]]++;
+                tk[2 * pos] = (int32_t)j;
+                tk[2 * pos + 1] = (int32_t)b;
+            }
+        });
+    }
     std::vector<size_t> off_pix(jobs.size() + 1, 0), off_cell(jobs.size() + 1, 0), off_blk(jobs.size() + 1, 0);
     for (size_t j = 0; j < jobs.size(); ++j) {
         off_pix[j + 1] = off_pix[j] + (size_t)jobs[j].W * jobs[j].H;

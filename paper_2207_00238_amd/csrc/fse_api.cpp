@@ -489,7 +489,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     a.counter = misc + 1;
     bool wide = false;
     for (auto& c : cls) wide |= (c.M == 64);
-    const int nw = wide ? 4 : (p->block_waves > 0 ? p->block_waves : 4);
+    const int nw = wide ? kWideWaves : (p->block_waves > 0 ? p->block_waves : 4);
     // Automatic grid: about twice the average number of blocks per dependency
     // level (per wavefront key for the other schedules).  A dependency chain
     // runs fastest when its blocks do not
@@ -701,12 +701,13 @@ fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t
     }
     bool wide = false;
     for (auto& c : cls) wide |= (c.M == 64);
-    std::vector<int> waves = wide ? std::vector<int>{4} : std::vector<int>{2, 4};
+    // launches with 64 x 64 windows have a fixed workgroup shape (block_waves 0)
+    std::vector<int> waves = wide ? std::vector<int>{0} : std::vector<int>{2, 4};
     double best_ms = 1e30;
-    int best_w = 4, best_g = 0;
+    int best_w = waves.front(), best_g = 0;
     hipStream_t st = (hipStream_t)stream;
     for (int w : waves) {
-        const int cap = persistent_grid(w, p->precision, wide);
+        const int cap = persistent_grid(wide ? kWideWaves : w, p->precision, wide);
         std::vector<int> grids{0};
         for (int g : {128, 256, 384, 512, 768, 1024})
             if (g < cap) grids.push_back(g);

@@ -7,7 +7,9 @@
 
 namespace fse {
 
-constexpr int kMaxThreads = 256;  // one processing block per workgroup of 1, 2 or 4 wave64
+// One processing block per workgroup of 1, 2 or 4 wave64 (32 x 32 windows);
+// launches that hold 64 x 64 windows use kWideWaves waves per workgroup.
+constexpr int kWideWaves = 8;
 constexpr int kMaxClasses = 3;
 
 struct ClassDev {

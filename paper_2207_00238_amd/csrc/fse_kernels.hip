@@ -105,11 +105,11 @@ constexpr int kBufDoubles64 = 64 * 65 + 64 * 64 * 2;      // w*s, then the weigh
 struct SharedHead {
     double twc32[32], tws32[32];
     double twc64[64], tws64[64];
-    double part[4];
+    double part[8];
     // per step (double-buffered) and wave: the wave winner's energy, spectrum
     // index and coefficient
-    double2 sK[2][4];  // energy, index (low word)
-    double2 sA[2][4];
+    double2 sK[2][8];  // energy, index (low word)
+    double2 sA[2][8];
     int job, blk, wait_fail;
     uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
     // coefficient list of the K steps (written during the steps, read by the
@@ -185,15 +185,16 @@ __device__ __forceinline__ int wave_argmax_lane(float e, IndexFn idx_of) {
     return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
 }
 
-// Winner among NW <= 4 wave slots held by lanes 0..NW-1 (energy e >= 0,
-// index idx): largest energy, then smallest index.  Maxima within the quad
-// by DPP; lanes >= NW are ignored.
+// Winner among NW <= 8 wave slots held by lanes 0..NW-1 (energy e >= 0,
+// index idx): largest energy, then smallest index.  Maxima over the first NW
+// lanes by DPP; lanes >= NW are ignored.
 template <int NW>
 __device__ __forceinline__ int slot_winner(double e, int idx) {
     constexpr unsigned long long SM = (1ull << NW) - 1;
     auto quad_umax = [](unsigned v) {
-        if constexpr (NW >= 2) v = dpp_umax_step<0xB1, 0xF, 0xF>(v);  // quad_perm [1,0,3,2]
-        if constexpr (NW >= 4) v = dpp_umax_step<0x4E, 0xF, 0xF>(v);  // quad_perm [2,3,0,1]
+        if constexpr (NW >= 2) v = dpp_umax_step<0xB1, 0xF, 0xF>(v);   // quad_perm [1,0,3,2]
+        if constexpr (NW >= 4) v = dpp_umax_step<0x4E, 0xF, 0xF>(v);   // quad_perm [2,3,0,1]
+        if constexpr (NW >= 8) v = dpp_umax_step<0x141, 0xF, 0xF>(v);  // row_half_mirror
         return (unsigned)__builtin_amdgcn_readlane((int)v, 0);
     };
     const unsigned hi = (unsigned)__double2hiint(e);
@@ -298,25 +299,32 @@ __device__ __forceinline__ flt4 mfma_step3(const float (&a)[4], const float (&b)
 // ---------------------------------------------------------------------------
 template <int M, int NW>
 struct TileMap {
-    static constexpr int TL = M / 16;                                    // tiles per dimension
-    static constexpr int NTJ = (M == 32) ? ((NW == 1) ? 2 : 1) : (4 / NW);  // column tiles per wave
-    static constexpr int NTI = (M == 32) ? ((NW == 4) ? 1 : 2) : 4;       // row tiles per wave
-    __device__ static int ti0(int wv) { return (M == 32 && NW == 4) ? (wv >> 1) : 0; }
+    static constexpr int TL = M / 16;  // tiles per dimension
+    // column tiles per wave
+    static constexpr int NTJ = (M == 32) ? ((NW == 1) ? 2 : 1) : ((NW <= 4) ? 4 / NW : 1);
+    // row tiles per wave
+    static constexpr int NTI = (M == 32) ? ((NW == 4) ? 1 : 2) : ((NW <= 4) ? 4 : 2);
+    __device__ static int ti0(int wv) {
+        return (M == 32) ? ((NW == 4) ? (wv >> 1) : 0) : ((NW == 8) ? (wv >> 2) * 2 : 0);
+    }
     __device__ static int tj0(int wv) {
-        return (M == 32) ? ((NW == 4) ? (wv & 1) : (NW == 2 ? wv : 0)) : wv * NTJ;
+        return (M == 32) ? ((NW == 4) ? (wv & 1) : (NW == 2 ? wv : 0)) : ((NW == 8) ? (wv & 3) : wv * NTJ);
     }
 };
 
 template <int NT>
 __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S);
 
-template <int M, int NW, int PREC>
+// NW waves compute the DFT and the K steps; the workgroup has NWG >= NW
+// waves, all of which stage the window, wait and synthesise (waves past NW
+// only keep the barriers of the DFT and the K steps).
+template <int M, int NW, int NWG, int PREC>
 __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& H, double* buf) {
     using T = typename PrecType<PREC>::T;
     using acc4 = typename std::conditional<PREC == kPrecF64, dbl4, flt4>::type;
     using TM = TileMap<M, NW>;
     constexpr bool F64 = PREC == kPrecF64;
-    constexpr int NT = 64 * NW;               // threads
+    constexpr int NT = 64 * NWG;              // threads
     constexpr int NTJ = TM::NTJ, NTI = TM::NTI;
     constexpr int EPT = NTI * NTJ * 4;        // spectrum elements per lane
     constexpr int NPIX = M * M / NT;          // window pixels per thread while staging
@@ -332,6 +340,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = t >> 6;
+    const bool active = wv < NW;  // wave-uniform
     const int ti0 = TM::ti0(wv), tj0 = TM::tj0(wv);
     const int4 d = const_load(J.desc + blk);
     const ClassDev& C = a.cls[d.z];
@@ -378,7 +387,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     __syncthreads();
     double W0 = H.part[0];
 #pragma unroll
-    for (int q = 1; q < NW; ++q) W0 += H.part[q];
+    for (int q = 1; q < NWG; ++q) W0 += H.part[q];
 
     // ---- DFT of one input (1: w -> weight spectrum in LDS, 0: w*s -> R in
     // registers) as F X F in two stages of MFMA GEMMs
@@ -388,7 +397,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     T rr[EPT], ri[EPT];
     auto dft = [&](const int inp) {
     acc4 t1[NTJ][TM::TL][2];  // [column tile][row tile][re, im]
-    {
+    if (active) {
         const T* X = inp ? Xw : Xs;
 #pragma unroll
         for (int cj = 0; cj < NTJ; ++cj) {
@@ -429,7 +438,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 
     // stage 2: F T for the wave's tiles; (F T)_re = C T_re + S T_im,
     // (F T)_im = C T_im - S T_re
-    {
+    if (active) {
 #pragma unroll
         for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
@@ -530,6 +539,10 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         const int jr = (e / NTJ) & 3, jci = e / (4 * NTJ), jcj = e % NTJ;
         return (jci * 16 + ROWR * jr) * M + jcj * 16;
     };
+    if (!active) {
+        if constexpr (NW > 1)
+            for (int it = 0; it < nsteps; ++it) __syncthreads();  // the step exchanges of the active waves
+    } else
     for (int it = 0; it < nsteps; ++it) {
         // first-index maximum over the lane's elements (pairwise tree over
         // increasing index: the right operand wins only when strictly larger);
@@ -756,12 +769,13 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blo
         if (job < 0) break;
         const JobDev J = const_load(a.jobs + job);
         if constexpr (WIDE) {
+            // 64 x 64 windows on all waves; 32 x 32 windows on four of them
             if (a.cls[J.desc[blk].z].M == 64)
-                process_block<64, NW, PREC>(a, J, blk, H, buf);
+                process_block<64, NW, NW, PREC>(a, J, blk, H, buf);
             else
-                process_block<32, NW, PREC>(a, J, blk, H, buf);
+                process_block<32, 4, NW, PREC>(a, J, blk, H, buf);
         } else {
-            process_block<32, NW, PREC>(a, J, blk, H, buf);
+            process_block<32, NW, NW, PREC>(a, J, blk, H, buf);
         }
         __syncthreads();
         if (t == 0) {
@@ -774,10 +788,10 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blo
 }
 
 static const void* kernel_for(int nw, int prec, bool wide) {
-    if (wide) {  // M = 64 blocks run with four waves
-        if (prec == kPrecF32) return (const void*)k_fse_blocks<4, 1, true>;
-        if (prec == kPrecBF16x3) return (const void*)k_fse_blocks<4, 2, true>;
-        return (const void*)k_fse_blocks<4, 0, true>;
+    if (wide) {  // launches with 64 x 64 windows run eight waves per workgroup
+        if (prec == kPrecF32) return (const void*)k_fse_blocks<kWideWaves, 1, true>;
+        if (prec == kPrecBF16x3) return (const void*)k_fse_blocks<kWideWaves, 2, true>;
+        return (const void*)k_fse_blocks<kWideWaves, 0, true>;
     }
 #define FSE_K(N, P) (const void*)k_fse_blocks<N, P, false>
     if (prec == kPrecF32) return nw == 1 ? FSE_K(1, 1) : nw == 2 ? FSE_K(2, 1) : FSE_K(4, 1);
@@ -793,7 +807,7 @@ int persistent_grid(int nw, int prec, bool wide) {
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const void* k = kernel_for(nw, prec, wide);
-    const int nthreads = 64 * (wide ? 4 : nw);
+    const int nthreads = 64 * (wide ? kWideWaves : nw);
     const int lds = (int)shared_bytes_blocks(wide);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nthreads, lds) != hipSuccess || per_cu < 1)
@@ -804,7 +818,7 @@ int persistent_grid(int nw, int prec, bool wide) {
 hipError_t launch_blocks_at(const LaunchArgs& a, int nw, int prec, bool wide, int grid, int ticket_base,
                             hipStream_t st) {
     const void* k = kernel_for(nw, prec, wide);
-    const int nthreads = 64 * (wide ? 4 : nw);
+    const int nthreads = 64 * (wide ? kWideWaves : nw);
     const int lds = (int)shared_bytes_blocks(wide);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     void* args[] = {(void*)&a, (void*)&ticket_base};

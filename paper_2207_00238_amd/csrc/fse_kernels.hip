@@ -347,6 +347,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const int B = C.B, b = C.b, K = C.K;
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
 
+    __builtin_amdgcn_s_setprio(0);  // staging before the wait: lowest issue priority
     // ---- stage the window: weights and weighted values --------------------
     // A window pixel is known (weight rho^dist), lost and owned by an earlier
     // block (reconstructed by the time this block runs in raster order:
@@ -506,6 +507,9 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // ---- wait for the earlier blocks this block depends on, then add their
     // reconstructed values to w*s
     wait_predecessors<NT>(a, J, blk, H);
+    // from here on the block is ready work: its waves issue ahead of the
+    // pre-wait staging of other blocks on the same SIMDs
+    __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int j = 0; j < NPIX; ++j) {
         if (recon_bits >> j & 1) {

@@ -102,6 +102,8 @@ def main():
                     help="comma-separated tile counts for the tile-framework comparison ('' = none)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="length of the served Poisson stream (0 = skip)")
     ap.add_argument("--no-precision-sweep", action="store_true", help="skip the FP32 / BF16x3 comparison")
+    ap.add_argument("--no-border-sweep", action="store_true",
+                    help="skip the tile-border sweep (PSNR vs stripe width d at N = 32 tiles)")
     ap.add_argument("--serve-rate", type=float, default=16.0, help="requests per second of the served stream")
     ap.add_argument("--only-batched", action="store_true",
                     help="measure the batched step only (for profiler runs): no secondary measurements")
@@ -262,6 +264,9 @@ def main():
                                     "blocks_executed": s["n_blocks"],
                                     "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole})
 
+    if args.tiles and not args.no_border_sweep:
+        result["tile_border_sweep"] = border_sweep(fse, torch, np, img, msk, common, wl, p_whole)
+
     if args.uhd_images > 0:
         result["uhd_tiled_batch"] = uhd_batch(fse, torch, np, args.uhd_images, args.steps)
 
@@ -288,6 +293,28 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def border_sweep(fse, torch, np, img, msk, common, wl, p_whole):
+    """The paper's tile-border experiment (Sec. IV, PSNR against the stripe
+    width d) on the first 1080p request: N = 32 tiles of the compact tiling,
+    stripes d in {0, 4, ..., 96} (multiples of the 4-pixel block grid), each
+    tile extrapolated as an independent image, cropped and merged.  PSNR over
+    the lost pixels against the ground truth, its change against the
+    whole-image result, and the executed blocks (stripes add work)."""
+    m = torch.from_numpy(wl.mask).bool()
+    gt = torch.from_numpy(wl.image).double()
+    out = torch.empty_like(img)
+    rows = []
+    for d in (0, 4, 8, 16, 24, 32, 48, 64, 96):
+        p = fse.fse_params_default(tiling=fse.FSE_TILED, n_tiles=32, overlap=d, align=4, **common)
+        fse.fse_extrapolate(img, msk, p, out)
+        s = fse.fse_last_stats()
+        e = (out.cpu().double().clamp(0, 255) - gt)[m]
+        ps = float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
+        rows.append({"d": d, "psnr_db": ps, "dpsnr_vs_whole_db": ps - p_whole, "blocks_executed": s["n_blocks"],
+                     "kernel_ms": s["kernel_ms"]})
+    return {"n_tiles": 32, "align": 4, "rows": rows}
 
 
 def uhd_batch(fse, torch, np, n, steps):

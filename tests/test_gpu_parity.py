@@ -220,3 +220,16 @@ def test_single_class_64_window():
     mask = synth.mask_blocks(128, 96, 8, 0.15, seed=94)
     cls = ((8, 28, 60),)
     _check(img, mask, cls)
+
+
+@pytest.mark.parametrize("d", [0, 4, 8])
+def test_tiled_small_stripes_match_tile_oracle(d):
+    # the tile-border sweep's narrow stripes (block-grid alignment 4), d = 0 included
+    img = synth.synth_image(160, 120, seed=45, period_max=128.0)
+    mask = synth.mask_blocks_and_pixels(160, 120, 4, 0.25, 0.01, seed=46)
+    cls = ((4, 14, 60),)
+    ref = O.image_tiled(img, mask, cls, 6, d, 4)
+    got, st = _run_tiled(img, mask, cls, 6, d, 4)
+    m = mask.astype(bool)
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got - ref)[m].max() <= TIGHT

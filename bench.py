@@ -305,16 +305,20 @@ def border_sweep(fse, torch, np, img, msk, common, wl, p_whole):
     m = torch.from_numpy(wl.mask).bool()
     gt = torch.from_numpy(wl.image).double()
     out = torch.empty_like(img)
-    rows = []
-    for d in (0, 4, 8, 16, 24, 32, 48, 64, 96):
-        p = fse.fse_params_default(tiling=fse.FSE_TILED, n_tiles=32, overlap=d, align=4, **common)
+    def run(tiling, d):
+        p = fse.fse_params_default(tiling=tiling, n_tiles=32, overlap=d, align=4, **common)
         fse.fse_extrapolate(img, msk, p, out)
         s = fse.fse_last_stats()
         e = (out.cpu().double().clamp(0, 255) - gt)[m]
         ps = float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
-        rows.append({"d": d, "psnr_db": ps, "dpsnr_vs_whole_db": ps - p_whole, "blocks_executed": s["n_blocks"],
-                     "kernel_ms": s["kernel_ms"]})
-    return {"n_tiles": 32, "align": 4, "rows": rows}
+        return {"d": d, "psnr_db": ps, "dpsnr_vs_whole_db": ps - p_whole, "blocks_executed": s["n_blocks"],
+                "kernel_ms": s["kernel_ms"]}
+
+    rows = [run(fse.FSE_TILED, d) for d in (0, 4, 8, 16, 24, 32, 48, 64, 96)]
+    # the same N and stripes with N full-height stripes instead of the compact
+    # grid of eq. (5): the overlap the compact tiling is there to avoid
+    vert = [run(fse.FSE_TILED_VERTICAL, d) for d in (0, 8, 32)]
+    return {"n_tiles": 32, "align": 4, "rows": rows, "vertical_stripes": vert}
 
 
 def uhd_batch(fse, torch, np, n, steps):

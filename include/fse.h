@@ -62,7 +62,8 @@ typedef int32_t fse_status_t;
 
 /* whole image with exact raster semantics, or the paper's tile framework */
 #define FSE_WHOLE 0
-#define FSE_TILED 1
+#define FSE_TILED 1          /* compact tiling, Algorithm 1 (Sec. III) */
+#define FSE_TILED_VERTICAL 2 /* N full-height stripes: the baseline the compact tiling improves on */
 
 #define FSE_MAX_CLASSES 3
 
@@ -112,8 +113,8 @@ typedef struct {
     double rho, gamma, recon_weight;
     int32_t precision; /* FSE_PREC_* */
     int32_t schedule;  /* FSE_SCHED_* */
-    int32_t tiling;    /* FSE_WHOLE or FSE_TILED */
-    int32_t n_tiles, overlap, align; /* FSE_TILED: tiles N, stripe d, grid alignment */
+    int32_t tiling;    /* FSE_WHOLE, FSE_TILED or FSE_TILED_VERTICAL */
+    int32_t n_tiles, overlap, align; /* tiled modes: tiles N, stripe d, grid alignment */
     int32_t workgroups;              /* persistent grid size; 0 = automatic (twice the mean blocks per wavefront key, at most the resident capacity) */
     int32_t block_waves;             /* wave64s per processing block: 1, 2 or 4; 0 = automatic */
     int32_t* trace_sel;
@@ -152,8 +153,18 @@ fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t 
                             fse_tile_t* tiles);
 
 /*
+ * N vertical stripes of the full height (all tiles in one row: widths as in
+ * eq. (5) with n_C = N), with the same stripe d and alignment as
+ * fse_plan_tiles.  The straightforward tiling that Sec. III improves on with
+ * compact tiles: it needs more overlap (stripes on long edges) for the same
+ * N.  Same arguments and errors as fse_plan_tiles.
+ */
+fse_status_t fse_plan_tiles_vertical(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align,
+                                     fse_tile_t* tiles);
+
+/*
  * Extrapolate the lost pixels of one image (Sec. II; with p->tiling ==
- * FSE_TILED through the tile framework of Sec. III).  Enqueued on `stream`;
+ * FSE_TILED or FSE_TILED_VERTICAL through the tile framework of Sec. III).  Enqueued on `stream`;
  * returns once the work is enqueued (the planner reads the mask back to the
  * host first, so the call waits for the mask to be ready).
  * Errors: INVALID_ARG (null pointers, size mismatch, parameter ranges),

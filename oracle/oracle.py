@@ -228,13 +228,26 @@ def tiling(W: int, H: int, N: int):
     return tiles
 
 
-def tiles_with_stripe(W: int, H: int, N: int, d: int, align: int = 1):
-    """Core tiles of :func:`tiling`, optionally with every interior edge moved
-    down to a multiple of ``align`` (block-grid alignment), each grown by the
-    stripe d on all four sides and clipped to the image.  Returns a list of
-    (core, extended) rectangles, each (x, y, w, h)."""
+def tiling_vertical(W: int, H: int, N: int):
+    """The straightforward alternative the compact tiling is measured against:
+    N vertical stripes of the full height, widths as in eq. (5) with all N
+    tiles in one row (ceil(W / N) for the first W mod N stripes, else floor)."""
+    tiles = []
+    x_T = 0
+    for j in range(1, N + 1):
+        w_T = -(-W // N) if j <= W % N else W // N
+        tiles.append((x_T, 0, w_T, H))
+        x_T += w_T
+    return tiles
+
+
+def tiles_with_stripe(W: int, H: int, N: int, d: int, align: int = 1, vertical: bool = False):
+    """Core tiles of :func:`tiling` (or of :func:`tiling_vertical`), optionally
+    with every interior edge moved down to a multiple of ``align`` (block-grid
+    alignment), each grown by the stripe d on all four sides and clipped to the
+    image.  Returns a list of (core, extended) rectangles, each (x, y, w, h)."""
     out = []
-    for (x, y, w, h) in tiling(W, H, N):
+    for (x, y, w, h) in (tiling_vertical(W, H, N) if vertical else tiling(W, H, N)):
         x1, y1 = x + w, y + h
         if align > 1:
             x0a = (x // align) * align
@@ -248,12 +261,13 @@ def tiles_with_stripe(W: int, H: int, N: int, d: int, align: int = 1):
     return out
 
 
-def image_tiled(img, mask, classes, N: int, d: int, align: int, rho=0.8, gamma=0.5, delta=0.5):
+def image_tiled(img, mask, classes, N: int, d: int, align: int, rho=0.8, gamma=0.5, delta=0.5,
+                vertical: bool = False):
     """Overlapping-tile framework on the CPU: each extended tile is extrapolated
     as an independent image, cropped to its core and merged (Sec. III)."""
     H, W = img.shape
     out = np.zeros((H, W))
-    for (core, ext) in tiles_with_stripe(W, H, N, d, align):
+    for (core, ext) in tiles_with_stripe(W, H, N, d, align, vertical):
         ex, ey, ew, eh = ext
         if ew <= 0 or eh <= 0:
             continue

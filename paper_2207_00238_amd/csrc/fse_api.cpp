@@ -114,7 +114,8 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
     if (p->precision != FSE_PREC_F64 && p->precision != FSE_PREC_F32 && p->precision != FSE_PREC_BF16X3)
         return FSE_ERR_INVALID_ARG;
     if (p->schedule < FSE_SCHED_PERSISTENT || p->schedule > FSE_SCHED_PER_BLOCK) return FSE_ERR_INVALID_ARG;
-    if (p->tiling != FSE_WHOLE && p->tiling != FSE_TILED) return FSE_ERR_INVALID_ARG;
+    if (p->tiling != FSE_WHOLE && p->tiling != FSE_TILED && p->tiling != FSE_TILED_VERTICAL)
+        return FSE_ERR_INVALID_ARG;
     cls.clear();
     for (int c = 0; c < p->n_classes; ++c) {
         const fse_class_t& k = p->classes[c];
@@ -126,7 +127,7 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
     }
     for (int c = 0; c + 1 < p->n_classes; ++c)
         if (cls[c].B <= cls[c + 1].B || cls[c].B % cls[c + 1].B) return FSE_ERR_INVALID_ARG;
-    if (p->tiling == FSE_TILED) {
+    if (p->tiling != FSE_WHOLE) {
         if (p->n_tiles < 1 || p->overlap < 0 || p->align < 1) return FSE_ERR_INVALID_ARG;
         if (p->align % cls.back().B != 0 || p->overlap % p->align != 0) return FSE_ERR_INVALID_ARG;
         if (p->align % cls.front().B != 0) return FSE_ERR_INVALID_ARG;
@@ -294,7 +295,9 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
             jobs.push_back(std::move(J));
         } else {
             std::vector<fse_tile_t> tiles(p->n_tiles);
-            s = fse_plan_tiles(W, H, p->n_tiles, p->overlap, p->align, tiles.data());
+            s = p->tiling == FSE_TILED_VERTICAL
+                    ? fse_plan_tiles_vertical(W, H, p->n_tiles, p->overlap, p->align, tiles.data())
+                    : fse_plan_tiles(W, H, p->n_tiles, p->overlap, p->align, tiles.data());
             if (s != FSE_OK) return s;
             for (auto& T : tiles) {
                 if (T.w <= 0 || T.h <= 0) continue;
@@ -609,11 +612,16 @@ fse_status_t fse_params_default(fse_params_t* p) {
     return FSE_OK;
 }
 
-fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align, fse_tile_t* tiles) {
+}  // extern "C"
+
+// Core tiles of a tiling, interior edges moved down to multiples of align,
+// grown by the stripe d and clipped to the image.
+static fse_status_t tiles_with_stripe(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align, bool vertical,
+                                      fse_tile_t* tiles) {
     if (W < 1 || H < 1 || N < 1 || d < 0 || align < 1 || !tiles) return FSE_ERR_INVALID_ARG;
     if ((int64_t)N > (int64_t)W * H) return FSE_ERR_INVALID_ARG;
     std::vector<int32_t> t;
-    if (!compact_tiling(W, H, N, t)) return FSE_ERR_INVALID_ARG;
+    if (!(vertical ? vertical_tiling(W, H, N, t) : compact_tiling(W, H, N, t))) return FSE_ERR_INVALID_ARG;
     for (int i = 0; i < N; ++i) {
         int x = t[4 * i], y = t[4 * i + 1];
         int x1 = x + t[4 * i + 2], y1 = y + t[4 * i + 3];
@@ -638,6 +646,17 @@ fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t 
         T.oh = std::max(0, std::min(H, y1 + d) - T.oy);
     }
     return FSE_OK;
+}
+
+extern "C" {
+
+fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align, fse_tile_t* tiles) {
+    return tiles_with_stripe(W, H, N, d, align, false, tiles);
+}
+
+fse_status_t fse_plan_tiles_vertical(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align,
+                                     fse_tile_t* tiles) {
+    return tiles_with_stripe(W, H, N, d, align, true, tiles);
 }
 
 fse_status_t fse_extrapolate(const fse_image_t* image, const fse_mask_t* mask, const fse_params_t* p,

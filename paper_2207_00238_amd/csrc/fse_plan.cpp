@@ -301,4 +301,16 @@ bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
     return true;
 }
 
+bool vertical_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
+    xywh.clear();
+    if (W < 1 || H < 1 || N < 1) return false;
+    int64_t xT = 0;
+    for (int64_t j = 1; j <= N; ++j) {
+        const int64_t wT = (j <= W % N) ? (W + N - 1) / N : W / N;
+        xywh.insert(xywh.end(), {(int32_t)xT, 0, (int32_t)wT, (int32_t)H});
+        xT += wT;
+    }
+    return true;
+}
+
 }  // namespace fse

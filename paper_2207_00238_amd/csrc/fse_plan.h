@@ -61,4 +61,7 @@ bool blocks_interact(const int32_t* desc_i, const int32_t* lbox_i, const int32_t
 // Algorithm 1 of the paper (eqs. (1)-(5)): core tiles x, y, w, h.
 bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh);
 
+// N full-height vertical stripes, widths as eq. (5) with all tiles in one row.
+bool vertical_tiling(int W, int H, int N, std::vector<int32_t>& xywh);
+
 }  // namespace fse

@@ -82,7 +82,7 @@ static int64_t request_bytes(const fse_image_t& im, const fse_params_t& p) {
     if (bmin < 1) bmin = 1;
     const int64_t cells = ((int64_t)im.width + bmin - 1) / bmin * (((int64_t)im.height + bmin - 1) / bmin);
     int64_t tiles_extra = 0;
-    if (p.tiling == FSE_TILED) tiles_extra = px;  // overlap stripes, generous
+    if (p.tiling != FSE_WHOLE) tiles_extra = px;  // overlap stripes, generous
     return (px + tiles_extra) * 8 + cells * (4 + 16 + 16 + 4 + 8);
 }
 
@@ -96,7 +96,7 @@ static bool same_params(const fse_params_t& a, const fse_params_t& b) {
         if (a.classes[c].block != b.classes[c].block || a.classes[c].border != b.classes[c].border ||
             a.classes[c].iters != b.classes[c].iters)
             return false;
-    if (a.tiling == FSE_TILED && (a.n_tiles != b.n_tiles || a.overlap != b.overlap || a.align != b.align)) return false;
+    if (a.tiling != FSE_WHOLE && (a.n_tiles != b.n_tiles || a.overlap != b.overlap || a.align != b.align)) return false;
     return true;
 }
 

@@ -25,14 +25,14 @@ FSE_ERR_BUSY = -8
 
 FSE_PREC_F64, FSE_PREC_F32, FSE_PREC_BF16X3 = 0, 1, 2
 FSE_SCHED_PERSISTENT, FSE_SCHED_WAVEFRONT, FSE_SCHED_PER_BLOCK = 0, 1, 2
-FSE_WHOLE, FSE_TILED = 0, 1
+FSE_WHOLE, FSE_TILED, FSE_TILED_VERTICAL = 0, 1, 2
 FSE_MAX_CLASSES = 3
 
 EXPORTED = [
     "fse_status_string", "fse_params_default", "fse_plan_tiles", "fse_extrapolate", "fse_extrapolate_batch",
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
     "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy",
-    "fse_autotune",
+    "fse_autotune", "fse_plan_tiles_vertical",
 ]
 
 
@@ -101,6 +101,8 @@ def lib():
         L.fse_params_default.argtypes = [P(fse_params_t)]
         L.fse_plan_tiles.restype = st
         L.fse_plan_tiles.argtypes = [ctypes.c_int32] * 5 + [P(fse_tile_t)]
+        L.fse_plan_tiles_vertical.restype = st
+        L.fse_plan_tiles_vertical.argtypes = [ctypes.c_int32] * 5 + [P(fse_tile_t)]
         L.fse_extrapolate.restype = st
         L.fse_extrapolate.argtypes = [P(fse_image_t), P(fse_mask_t), P(fse_params_t), P(fse_image_t), ctypes.c_void_p]
         L.fse_extrapolate_batch.restype = st
@@ -168,6 +170,12 @@ def fse_params_default(**overrides) -> fse_params_t:
 def fse_plan_tiles(W: int, H: int, N: int, d: int, align: int = 1):
     tiles = (fse_tile_t * N)()
     check(lib().fse_plan_tiles(W, H, N, d, align, tiles), "fse_plan_tiles")
+    return [((t.x, t.y, t.w, t.h), (t.ox, t.oy, t.ow, t.oh)) for t in tiles]
+
+
+def fse_plan_tiles_vertical(W: int, H: int, N: int, d: int, align: int = 1):
+    tiles = (fse_tile_t * N)()
+    check(lib().fse_plan_tiles_vertical(W, H, N, d, align, tiles), "fse_plan_tiles_vertical")
     return [((t.x, t.y, t.w, t.h), (t.ox, t.oy, t.ow, t.oh)) for t in tiles]
 
 

@@ -35,6 +35,14 @@ def test_plan_tiles_matches_oracle(W, H, N, d, align):
     assert [(tuple(c), tuple(e)) for c, e in got] == [(tuple(c), tuple(e)) for c, e in ref]
 
 
+@pytest.mark.parametrize("W,H,N,d,align", [(1024, 480, 22, 0, 1), (1920, 1080, 32, 32, 4), (3840, 2160, 64, 32, 16),
+                                           (37, 11, 5, 3, 1), (1000, 999, 13, 8, 4), (128, 128, 1, 32, 16)])
+def test_plan_tiles_vertical_matches_oracle(W, H, N, d, align):
+    got = fse.fse_plan_tiles_vertical(W, H, N, d, align)
+    ref = O.tiles_with_stripe(W, H, N, d, align, vertical=True)
+    assert [(tuple(c), tuple(e)) for c, e in got] == [(tuple(c), tuple(e)) for c, e in ref]
+
+
 def test_plan_tiles_rejects_bad_arguments():
     L = fse.lib()
     tiles = (fse.fse_tile_t * 4)()

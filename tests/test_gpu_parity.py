@@ -129,14 +129,16 @@ def test_repeat_calls_are_deterministic():
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
-def _run_tiled(img, mask, classes, N, d, align, **kw):
+def _run_tiled(img, mask, classes, N, d, align, tiling=None, **kw):
     import torch
     from paper_2207_00238_amd import fse
     dev = torch.device("cuda:0")
     ti = torch.from_numpy(np.ascontiguousarray(img, dtype=np.float32)).to(dev)
     tm = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).to(dev)
     out = torch.full_like(ti, -12345.0)
-    p = fse.fse_params_default(classes=classes, tiling=fse.FSE_TILED, n_tiles=N, overlap=d, align=align, **kw)
+    if tiling is None:
+        tiling = fse.FSE_TILED
+    p = fse.fse_params_default(classes=classes, tiling=tiling, n_tiles=N, overlap=d, align=align, **kw)
     fse.fse_extrapolate(ti, tm, p, out)
     torch.cuda.synchronize()
     return out.cpu().numpy(), fse.fse_last_stats()
@@ -149,6 +151,21 @@ def test_tiled_matches_tile_oracle(N, d):
     cls = ((4, 14, 60),)
     ref = O.image_tiled(img, mask, cls, N, d, 16)
     got, st = _run_tiled(img, mask, cls, N, d, 16)
+    assert st["n_jobs"] == N
+    m = mask.astype(bool)
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got - ref)[m].max() <= TIGHT
+
+
+@pytest.mark.parametrize("N,d,align", [(5, 32, 4), (9, 8, 4), (3, 0, 4)])
+def test_vertical_tiled_matches_tile_oracle(N, d, align):
+    # full-height stripes (the tiling that Sec. III sets the compact one against)
+    from paper_2207_00238_amd import fse
+    img = synth.synth_image(200, 136, seed=47, period_max=128.0)
+    mask = synth.mask_blocks_and_pixels(200, 136, 4, 0.25, 0.01, seed=48)
+    cls = ((4, 14, 60),)
+    ref = O.image_tiled(img, mask, cls, N, d, align, vertical=True)
+    got, st = _run_tiled(img, mask, cls, N, d, align, tiling=fse.FSE_TILED_VERTICAL)
     assert st["n_jobs"] == N
     m = mask.astype(bool)
     assert np.array_equal(got[~m], img[~m])

@@ -97,3 +97,26 @@ def test_large_n_rows_clipped_still_partition(W, H, N):
     assert all(t[2] >= 0 and t[3] >= 0 for t in tiles)
     cov = _cover(W, H, tiles)
     assert (cov == 1).all()
+
+
+@pytest.mark.parametrize("W,H,N", [(1024, 480, 22), (37, 11, 5), (100, 300, 7), (64, 64, 64)])
+def test_vertical_tiling_partition_and_widths(W, H, N):
+    # N full-height stripes, widths differing by at most one pixel, the wider
+    # ones first (eq. (5) with a single row)
+    tiles = O.tiling_vertical(W, H, N)
+    assert len(tiles) == N
+    cov = _cover(W, H, tiles)
+    assert (cov == 1).all()
+    ws = [w for (_, _, w, _) in tiles]
+    assert all(h == H and y == 0 for (_, y, _, h) in tiles)
+    assert max(ws) - min(ws) <= 1 and ws == sorted(ws, reverse=True)
+    assert sum(ws) == W
+
+
+def test_vertical_stripes_overlap_more_than_compact():
+    # the reason for the compact tiling: for the same N and d the stripes of
+    # the vertical tiling cover more extra pixels (Sec. III)
+    W, H, N, d = 1920, 1080, 32, 32
+    def extra(tiles):
+        return sum(ew * eh for (_, (ex, ey, ew, eh)) in tiles) - W * H
+    assert extra(O.tiles_with_stripe(W, H, N, d, 4, vertical=True)) > 1.5 * extra(O.tiles_with_stripe(W, H, N, d, 4))

@@ -103,6 +103,11 @@ typedef struct {
  * rho in (0,1]: isotropic weight decay rho^distance; recon_weight in (0,1]:
  * extra factor for pixels reconstructed by earlier blocks; gamma in (0,2):
  * orthogonality-deficiency compensation.
+ * Tiled modes: align is a multiple of every class's block edge, so tile
+ * cores start on the image's block grid; the stripe d is any d >= 0.  Each
+ * extended tile is processed as an image of its own (Sec. III), with its
+ * block grid anchored at its own top-left corner: a d that is not a
+ * multiple of align shifts that grid against the image's.
  * trace_sel (device, may be NULL): receives the selected index u*M+v of
  * every step of every block, at [raster_block_index * trace_stride + step];
  * trace_capacity bounds the number of blocks traced.

@@ -129,7 +129,7 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
         if (cls[c].B <= cls[c + 1].B || cls[c].B % cls[c + 1].B) return FSE_ERR_INVALID_ARG;
     if (p->tiling != FSE_WHOLE) {
         if (p->n_tiles < 1 || p->overlap < 0 || p->align < 1) return FSE_ERR_INVALID_ARG;
-        if (p->align % cls.back().B != 0 || p->overlap % p->align != 0) return FSE_ERR_INVALID_ARG;
+        if (p->align % cls.back().B != 0) return FSE_ERR_INVALID_ARG;
         if (p->align % cls.front().B != 0) return FSE_ERR_INVALID_ARG;
     }
     if (p->block_waves != 0 && p->block_waves != 1 && p->block_waves != 2 && p->block_waves != 4)

@@ -28,7 +28,8 @@ def test_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("W,H,N,d,align", [(1024, 480, 22, 0, 1), (1920, 1080, 32, 32, 1), (3840, 2160, 64, 32, 16),
                                            (480, 1920, 7, 8, 4), (1000, 999, 13, 3, 1), (128, 128, 1, 32, 16),
-                                           (1920, 1080, 1024, 32, 16), (1920, 1080, 256, 32, 16)])
+                                           (1920, 1080, 1024, 32, 16), (1920, 1080, 256, 32, 16),
+                                           (1920, 1080, 32, 1, 4), (1920, 1080, 32, 2, 4), (200, 136, 6, 6, 4)])
 def test_plan_tiles_matches_oracle(W, H, N, d, align):
     got = fse.fse_plan_tiles(W, H, N, d, align)
     ref = O.tiles_with_stripe(W, H, N, d, align)

@@ -157,7 +157,7 @@ def test_tiled_matches_tile_oracle(N, d):
     assert np.abs(got - ref)[m].max() <= TIGHT
 
 
-@pytest.mark.parametrize("N,d,align", [(5, 32, 4), (9, 8, 4), (3, 0, 4)])
+@pytest.mark.parametrize("N,d,align", [(5, 32, 4), (9, 8, 4), (3, 0, 4), (4, 3, 4)])
 def test_vertical_tiled_matches_tile_oracle(N, d, align):
     # full-height stripes (the tiling that Sec. III sets the compact one against)
     from paper_2207_00238_amd import fse
@@ -239,9 +239,10 @@ def test_single_class_64_window():
     _check(img, mask, cls)
 
 
-@pytest.mark.parametrize("d", [0, 4, 8])
+@pytest.mark.parametrize("d", [0, 1, 2, 4, 6, 8])
 def test_tiled_small_stripes_match_tile_oracle(d):
-    # the tile-border sweep's narrow stripes (block-grid alignment 4), d = 0 included
+    # the tile-border sweep's narrow stripes (cores on the 4-pixel block grid),
+    # d = 0 included; d = 1, 2, 6 put each tile's own block grid off the image's
     img = synth.synth_image(160, 120, seed=45, period_max=128.0)
     mask = synth.mask_blocks_and_pixels(160, 120, 4, 0.25, 0.01, seed=46)
     cls = ((4, 14, 60),)

@@ -85,6 +85,40 @@ def cpu_baseline():
                       f"single-threaded FP64 C oracle)"}
 
 
+def cpu_tile_framework():
+    """The paper's framework on the host (Sec. III): the first 1080p request cut
+    into N = (host threads, at most 16) compact tiles with stripe d = 32, each
+    extended tile extrapolated by the FP64 C oracle as an image of its own on
+    a thread of its own, cores cropped and merged.  Rate in the request's lost
+    blocks per wall second, as for the GPU tile rows."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle
+    from paper_2207_00238_amd import synth
+
+    wl = synth.workload("hd")
+    H, W = wl.mask.shape
+    n = max(1, min(16, len(os.sched_getaffinity(0))))
+    tiles = [t for t in oracle.tiles_with_stripe(W, H, n, 32, 4) if t[1][2] > 0 and t[1][3] > 0]
+    nb = len(oracle.plan(wl.mask, wl.classes)[0])
+    out = np.zeros((H, W))
+
+    def one(t):
+        (cx, cy, cw, ch), (ex, ey, ew, eh) = t
+        sub = oracle.image(wl.image[ey:ey + eh, ex:ex + ew], wl.mask[ey:ey + eh, ex:ex + ew], wl.classes,
+                           rho=wl.rho, gamma=wl.gamma, delta=wl.recon_weight)
+        out[cy:cy + ch, cx:cx + cw] = sub[cy - ey:cy - ey + ch, cx - ex:cx - ex + cw]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        list(ex.map(one, tiles))
+    dt = time.perf_counter() - t0
+    return {"value": nb / dt, "unit": "blocks/s", "cores": n, "kind": "oracle",
+            "sample": f"first 1920x1080 request ({nb} lost blocks), {len(tiles)} compact tiles with d = 32, one "
+                      f"FP64 C oracle thread per tile, {dt:.1f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +130,8 @@ def main():
                     help="3840x2160 mixed-loss images for the tiled batch measurement (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-block comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams the timed batched steps rotate over (1 = one step at a time)")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--block-waves", type=int, default=4)
     ap.add_argument("--tiles", type=str, default="64",
@@ -114,6 +150,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the method's tiles are "
               "independent, so several GPUs would each run their own share", file=sys.stderr)
         sys.exit(2)
+    if args.streams < 1:
+        ap.error("--streams must be at least 1")
 
     import numpy as np
     import torch
@@ -151,6 +189,9 @@ def main():
         fse.fse_extrapolate_batch(imgs, msks, params, outs, stream)
     st = fse.fse_last_stats()
     n_blocks = st["n_blocks"]
+
+    # serialised steps: each launch alone on the device (launch duration,
+    # roofline and step latency are taken here)
     step_ms, kern_ms, plan_ms = [], [], []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -164,9 +205,33 @@ def main():
         if s["device_error"]:
             raise RuntimeError("device dependency wait timed out")
     torch.cuda.synchronize()
-    total = time.perf_counter() - t_all
+    total_serial = time.perf_counter() - t_all
+    serial_outs = [o.clone() for o in outs]
+    batched_out0 = serial_outs[0]
+
+    # pipelined steps: consecutive batches on `streams` streams (each with
+    # its own workspace and outputs), so the host planning of a batch and the
+    # launches of the batches before it run at the same time and the
+    # dependency chains of two or three batches share the CUs
+    pipe = None
+    total = total_serial
+    if args.streams > 1:
+        strs = [stream] + [torch.cuda.Stream() for _ in range(args.streams - 1)]
+        pouts = [outs] + [[torch.empty_like(t) for t in imgs] for _ in range(args.streams - 1)]
+        for j in range(1, args.streams):
+            fse.fse_extrapolate_batch(imgs, msks, params, pouts[j], strs[j])
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for i in range(args.steps):
+            fse.fse_extrapolate_batch(imgs, msks, params, pouts[i % args.streams], strs[i % args.streams])
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        if fse.fse_last_stats()["device_error"]:
+            raise RuntimeError("device dependency wait timed out")
+        same = all(torch.equal(a, b) for o in pouts for a, b in zip(o, serial_outs))
+        pipe = {"streams": args.streams, "ms_per_step": total * 1e3 / args.steps,
+                "bitwise_equal_to_serialised": bool(same)}
     value = n_blocks * args.steps / total
-    batched_out0 = outs[0].clone()
 
     flops = block_flops(M, K, B)
     k_avg = float(np.mean(kern_ms)) / 1e3
@@ -191,7 +256,10 @@ def main():
                                f"gamma={wl.gamma}, exact raster semantics per request",
                    "schedule": f"one persistent dependency-driven launch per step, "
                                f"{params.block_waves} waves/block, grid {params.workgroups or 'automatic'}"
-                               + (" (autotuned)" if tuned else "")},
+                               + (" (autotuned)" if tuned else "")
+                               + (f", consecutive steps on {args.streams} streams" if args.streams > 1 else "")},
+        "serialised": {"value": n_blocks * args.steps / total_serial, "ms_per_step": total_serial * 1e3 / args.steps},
+        "pipelined": pipe,
         "step_p50_ms": float(np.percentile(step_ms, 50)),
         "step_p99_ms": float(np.percentile(step_ms, 99)),
         "kernel_ms": float(np.mean(kern_ms)),
@@ -274,7 +342,10 @@ def main():
         result["precision_sweep"] = precision_sweep(fse, torch, np, img, msk, common, wl, K)
 
     if args.serve_seconds > 0:
-        result["served"] = serve_stream(fse, torch, np, imgs, msks, params, args.serve_rate, args.serve_seconds,
+        # served launches hold one to a few requests: the automatic grid (sized
+        # from each launch's own blocks per wavefront key), not the batch's
+        p_serve = fse.fse_params_default(**{**common, "workgroups": 0, "block_waves": params.block_waves})
+        result["served"] = serve_stream(fse, torch, np, imgs, msks, p_serve, args.serve_rate, args.serve_seconds,
                                         nb1, res_single)
 
     if not args.no_plain:
@@ -292,6 +363,8 @@ def main():
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
+        if not args.only_batched:
+            result["cpu_baseline"]["tile_framework"] = cpu_tile_framework()
     print(json.dumps(result), flush=True)
 
 

@@ -218,19 +218,36 @@ def main():
     if args.streams > 1:
         strs = [stream] + [torch.cuda.Stream() for _ in range(args.streams - 1)]
         pouts = [outs] + [[torch.empty_like(t) for t in imgs] for _ in range(args.streams - 1)]
-        for j in range(1, args.streams):
-            fse.fse_extrapolate_batch(imgs, msks, params, pouts[j], strs[j])
+
+        def rotate(p, steps):
+            for i in range(steps):
+                fse.fse_extrapolate_batch(imgs, msks, p, pouts[i % args.streams], strs[i % args.streams])
+
+        # grid for overlapping steps (untimed): the step-at-a-time choice
+        # above need not be the best once several launches share the CUs
+        p_pipe = params
+        if args.workgroups == 0:
+            cands = []
+            for wg in dict.fromkeys([params.workgroups, 0, 768, 1024]):
+                p_c = fse.fse_params_default(**{**common, "workgroups": wg, "block_waves": params.block_waves})
+                rotate(p_c, args.streams)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rotate(p_c, 2 * args.streams)
+                torch.cuda.synchronize()
+                cands.append((time.perf_counter() - t0, wg, p_c))
+            _, _, p_pipe = min(cands, key=lambda c: c[0])
+        rotate(p_pipe, args.streams)
         torch.cuda.synchronize()
         t_all = time.perf_counter()
-        for i in range(args.steps):
-            fse.fse_extrapolate_batch(imgs, msks, params, pouts[i % args.streams], strs[i % args.streams])
+        rotate(p_pipe, args.steps)
         torch.cuda.synchronize()
         total = time.perf_counter() - t_all
         if fse.fse_last_stats()["device_error"]:
             raise RuntimeError("device dependency wait timed out")
         same = all(torch.equal(a, b) for o in pouts for a, b in zip(o, serial_outs))
-        pipe = {"streams": args.streams, "ms_per_step": total * 1e3 / args.steps,
-                "bitwise_equal_to_serialised": bool(same)}
+        pipe = {"streams": args.streams, "workgroups": p_pipe.workgroups or "automatic",
+                "ms_per_step": total * 1e3 / args.steps, "bitwise_equal_to_serialised": bool(same)}
     value = n_blocks * args.steps / total
 
     flops = block_flops(M, K, B)
@@ -257,7 +274,8 @@ def main():
                    "schedule": f"one persistent dependency-driven launch per step, "
                                f"{params.block_waves} waves/block, grid {params.workgroups or 'automatic'}"
                                + (" (autotuned)" if tuned else "")
-                               + (f", consecutive steps on {args.streams} streams" if args.streams > 1 else "")},
+                               + (f"; consecutive steps on {args.streams} streams, grid "
+                                  f"{pipe['workgroups']}" if pipe else "")},
         "serialised": {"value": n_blocks * args.steps / total_serial, "ms_per_step": total_serial * 1e3 / args.steps},
         "pipelined": pipe,
         "step_p50_ms": float(np.percentile(step_ms, 50)),

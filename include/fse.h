@@ -222,7 +222,10 @@ typedef struct fse_server fse_server_t;
 
 typedef struct {
     int64_t hbm_budget_bytes; /* device memory the server may hold for requests */
-    int32_t max_slots;        /* requests resident at once */
+    int32_t max_slots;        /* launches in flight at once (1..16), each on a stream with a hardware queue
+                                 of its own (created with a CU mask of all CUs: plain streams share the
+                                 runtime's small queue pool, where two launches would run one after the
+                                 other) */
     int32_t device;           /* HIP device ordinal */
     int32_t workgroups;       /* persistent grid size, 0 = automatic */
 } fse_serve_config_t;

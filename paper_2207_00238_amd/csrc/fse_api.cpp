@@ -34,11 +34,10 @@ fse_status_t from_hip(hipError_t e) {
     return FSE_ERR_DEVICE;
 }
 
-hipError_t DevBuf::ensure(size_t n) {
+hipError_t DevBuf::ensure(size_t n, std::vector<void*>& retired) {
     if (n <= cap) return hipSuccess;
     if (p) {
-        hipError_t e = hipFree(p);
-        if (e != hipSuccess) return e;
+        retired.push_back(p);
         p = nullptr;
         cap = 0;
     }
@@ -87,6 +86,10 @@ void release_all_workspaces() {
 
 void Workspace::free_all() {
     for (DevBuf* b : {&recon, &owner, &desc, &lbox, &done, &tickets, &jobs, &misc, &tabs}) b->release();
+    for (void* q : retired_dev) hipFree(q);
+    for (void* q : retired_host) hipHostFree(q);
+    retired_dev.clear();
+    retired_host.clear();
     tab_key.clear();
     if (host_mask) hipHostFree(host_mask);
     if (stage) hipHostFree(stage);
@@ -174,7 +177,7 @@ static fse_status_t upload_tables(Workspace& ws, const std::vector<ClassCfg>& cl
                     h[off + m * c.M + n] = std::pow(rho, std::sqrt((m - ctr) * (m - ctr) + (n - ctr) * (n - ctr)));
             off += (size_t)c.M * c.M;
         }
-        hipError_t e = ws.tabs.ensure(total * sizeof(double));
+        hipError_t e = ws.tabs.ensure(total * sizeof(double), ws.retired_dev);
         if (e != hipSuccess) return from_hip(e);
         e = hipMemcpyAsync(ws.tabs.p, h.data(), total * sizeof(double), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return from_hip(e);
@@ -273,12 +276,15 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     std::vector<size_t> moff(n + 1, 0);
     for (int i = 0; i < n; ++i) moff[i + 1] = moff[i] + (size_t)images[i].width * images[i].height;
     if (ws.host_mask_cap < moff[n]) {
-        if (ws.host_mask) hipHostFree(ws.host_mask);
+        // pinned memory grows with headroom; the old block is retired, not
+        // freed (hipHostFree waits for the whole device)
+        if (ws.host_mask) ws.retired_host.push_back(ws.host_mask);
         ws.host_mask = nullptr;
         ws.host_mask_cap = 0;
-        if ((e = hipHostMalloc((void**)&ws.host_mask, moff[n], hipHostMallocDefault)) != hipSuccess)
+        const size_t want = moff[n] + moff[n] / 4;
+        if ((e = hipHostMalloc((void**)&ws.host_mask, want, hipHostMallocDefault)) != hipSuccess)
             return from_hip(e);
-        ws.host_mask_cap = moff[n];
+        ws.host_mask_cap = want;
     }
     for (int i = 0; i < n; ++i) {
         const int W = images[i].width, H = images[i].height;
@@ -380,14 +386,15 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         n_cells += J.plan->owner.size();
         n_blk += J.plan->desc.size() / 4;
     }
-    if ((e = ws.recon.ensure(n_pix * sizeof(double))) != hipSuccess) return from_hip(e);
-    if ((e = ws.owner.ensure(std::max<size_t>(n_cells, 1) * 4)) != hipSuccess) return from_hip(e);
-    if ((e = ws.desc.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
-    if ((e = ws.lbox.ensure(std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
-    if ((e = ws.done.ensure(std::max<size_t>(n_blk, 1) * 4)) != hipSuccess) return from_hip(e);
-    if ((e = ws.tickets.ensure((size_t)std::max<int64_t>(ntk, 1) * 8)) != hipSuccess) return from_hip(e);
-    if ((e = ws.jobs.ensure(jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
-    if ((e = ws.misc.ensure(64)) != hipSuccess) return from_hip(e);
+    auto grow = [&](DevBuf& b, size_t bytes) { return b.ensure(bytes, ws.retired_dev); };
+    if ((e = grow(ws.recon, n_pix * sizeof(double))) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.owner, std::max<size_t>(n_cells, 1) * 4)) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.desc, std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.lbox, std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.done, std::max<size_t>(n_blk, 1) * 4)) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.tickets, (size_t)std::max<int64_t>(ntk, 1) * 8)) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.jobs, jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
+    if ((e = grow(ws.misc, 64)) != hipSuccess) return from_hip(e);
 
     // host images of the tables in pinned staging memory, one upload each
     const size_t b_owner = std::max<size_t>(n_cells, 1) * 4, b_desc = std::max<size_t>(n_blk, 1) * 16,
@@ -396,11 +403,12 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
                  o_lbox = o_desc + ((b_desc + 255) & ~(size_t)255), o_tk = o_lbox + ((b_desc + 255) & ~(size_t)255),
                  o_jobs = o_tk + ((b_tk + 255) & ~(size_t)255), stage_bytes = o_jobs + b_jobs + 256;
     if (ws.stage_cap < stage_bytes) {
-        if (ws.stage) (void)hipHostFree(ws.stage);
+        if (ws.stage) ws.retired_host.push_back(ws.stage);
         ws.stage = nullptr;
         ws.stage_cap = 0;
-        if ((e = hipHostMalloc((void**)&ws.stage, stage_bytes, hipHostMallocDefault)) != hipSuccess) return from_hip(e);
-        ws.stage_cap = stage_bytes;
+        const size_t want = stage_bytes + stage_bytes / 4;
+        if ((e = hipHostMalloc((void**)&ws.stage, want, hipHostMallocDefault)) != hipSuccess) return from_hip(e);
+        ws.stage_cap = want;
     }
     int32_t* h_owner = (int32_t*)(ws.stage + o_owner);
     int32_t* h_desc = (int32_t*)(ws.stage + o_desc);

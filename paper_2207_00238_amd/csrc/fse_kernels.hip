@@ -95,11 +95,15 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
 // LDS layout.  The area holds w*s (M x (M+1)), kept from before the
 // dependency wait until the DFT of w*s after it, followed by a region that
 // first holds w (M x (M+1)) and then the weight spectrum for the K steps
-// (M = 32: 64 x 32 complex with duplicated rows; M = 64: 64 x 64 complex).
-// The coefficient list lives in the head.  Sized for M = 32 (41 KB) or, when a
-// launch has M = 64 blocks, for M = 64 (97 KB).
+// (M = 32: (32 + kWrapRows) x 32 complex, rows 0 .. kWrapRows-1 repeated
+// after row 31; M = 64: 64 x 64 complex).  The coefficient list lives in the
+// head.  Sized for M = 32 (38 KB with the head: four blocks fit in a CU's
+// 160 KB) or, when a launch has M = 64 blocks, for M = 64 (97 KB).
 constexpr int kMaxK = 256;
-constexpr int kBufDoubles32 = 32 * 33 + 2 * 32 * 32 * 2;  // w*s, then the duplicated weight spectrum
+// A lane's four elements of one row tile lie on rows base + ROWR r (r < 4,
+// ROWR <= 4 rows): with the base reduced mod 32 they stay below 32 + 12.
+constexpr int kWrapRows = 12;
+constexpr int kBufDoubles32 = 32 * 33 + (32 + kWrapRows) * 32 * 2;  // w*s, then the weight spectrum
 constexpr int kBufDoubles64 = 64 * 65 + 64 * 64 * 2;      // w*s, then the weight spectrum
 
 struct SharedHead {
@@ -334,7 +338,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     constexpr int LD = M + 1;                 // padded row stride of X
     constexpr int MASK = M - 1;
     constexpr int LOGM = (M == 32) ? 5 : 6;
-    constexpr bool DUP = (M == 32);           // weight spectrum rows duplicated
+    constexpr bool DUP = (M == 32);           // weight spectrum rows 0 .. kWrapRows-1 repeated after row M-1
     const double* twc = (M == 32) ? H.twc32 : H.twc64;
     const double* tws = (M == 32) ? H.tws32 : H.tws64;
     const int t = threadIdx.x;
@@ -355,7 +359,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // so the weights, W0, the known part of w*s and the weight spectrum are
     // formed before the dependency wait; only the reconstructed values wait.
     T* Xs = reinterpret_cast<T*>(buf);  // w * s, [m][n] stride LD
-    T* Wd = Xs + M * LD;                // weight spectrum [DUP ? 2M : M][M] complex
+    T* Wd = Xs + M * LD;                // weight spectrum [DUP ? M + kWrapRows : M][M] complex
     T* Xw = Wd;                         // w, staged where the weight spectrum goes
     const int Bm = a.Bmin;
     double wsum = 0.0;
@@ -385,10 +389,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     }
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
     if (lane == 0) H.part[wv] = wsum;
-    __syncthreads();
-    double W0 = H.part[0];
-#pragma unroll
-    for (int q = 1; q < NWG; ++q) W0 += H.part[q];
+    __syncthreads();  // the per-wave sums of w stay in LDS until the steps need W0
 
     // ---- DFT of one input (1: w -> weight spectrum in LDS, 0: w*s -> R in
     // registers) as F X F in two stages of MFMA GEMMs
@@ -397,6 +398,12 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const int li = lane & 15, lk = lane >> 4;
     T rr[EPT], ri[EPT];
     auto dft = [&](const int inp) {
+    // the lane coordinates again, opaque to the compiler: the per-lane twiddle
+    // addresses derived from them are recomputed in each DFT (a few integer
+    // operations) instead of being hoisted out of the block loop, where they
+    // would hold two dozen registers for the whole loop
+    int li = lane & 15, lk = lane >> 4;
+    asm volatile("" : "+v"(li), "+v"(lk));
     acc4 t1[NTJ][TM::TL][2];  // [column tile][row tile][re, im]
     if (active) {
         const T* X = inp ? Xw : Xs;
@@ -486,7 +493,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                     if (inp == 1) {
                         Wd[(k * M + l) * 2] = ore[r];
                         Wd[(k * M + l) * 2 + 1] = oim[r];
-                        if (DUP) {
+                        if (DUP && k < kWrapRows) {
                             Wd[((k + M) * M + l) * 2] = ore[r];
                             Wd[((k + M) * M + l) * 2 + 1] = oim[r];
                         }
@@ -532,6 +539,12 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // then the shifted weight spectrum is gathered from LDS for the update.
     constexpr int ROWK = F64 ? 1 : 4;  // row step per lk
     constexpr int ROWR = F64 ? 4 : 1;  // row step per r
+    static_assert(!DUP || 3 * ROWR <= kWrapRows, "wrapped weight-spectrum rows");
+    // W0 from the per-wave sums (read here rather than before the DFTs and
+    // the wait, across which it would occupy registers)
+    double W0 = H.part[0];
+#pragma unroll
+    for (int q = 1; q < NWG; ++q) W0 += H.part[q];
     // uniform across the block: lets the loop run under scalar control
     const bool live = __builtin_amdgcn_readfirstlane((int)(W0 > 0.0)) != 0;
     const int nsteps = live ? __builtin_amdgcn_readfirstlane(K) : 0;
@@ -550,15 +563,16 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     for (int it = 0; it < nsteps; ++it) {
         // first-index maximum over the lane's elements (pairwise tree over
         // increasing index: the right operand wins only when strictly larger);
-        // the tree carries the element's spectrum index and value
+        // the tree carries the element's number (small constants, no
+        // registers) and value; the spectrum index follows from the number
         T ev[EPT], vr[EPT], vi[EPT];
-        int ix[EPT];
+        int ex[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             ev[j] = rr[j] * rr[j] + ri[j] * ri[j];
             vr[j] = rr[j];
             vi[j] = ri[j];
-            ix[j] = lane_idx + elem_offset(j);
+            ex[j] = j;
         }
 #pragma unroll
         for (int st = 1; st < EPT; st <<= 1) {
@@ -566,12 +580,13 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             for (int j = 0; j + st < EPT; j += 2 * st) {
                 const bool take = ev[j + st] > ev[j];
                 ev[j] = take ? ev[j + st] : ev[j];
-                ix[j] = take ? ix[j + st] : ix[j];
+                ex[j] = take ? ex[j + st] : ex[j];
                 vr[j] = take ? vr[j + st] : vr[j];
                 vi[j] = take ? vi[j + st] : vi[j];
             }
         }
         const T lm = ev[0];
+        int ix[1] = {lane_idx + elem_offset(ex[0])};
         // the lane's candidate coefficient, formed before the wave reduction
         // so that it is ready when the winner lane publishes it (the empty
         // asm keeps it from being sunk into the winner's branch)
@@ -615,8 +630,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int e = (ci_ * 4 + r) * NTJ + cj;
-                    // DUP: rows row0 + M + ROWR r lie in [1, 2M) of the duplicated table
-                    const T* w = DUP ? (Wd + (((row0 + M) << LOGM) + col) * 2 + r * (ROWR * M * 2))
+                    // DUP: rows (row0 mod M) + ROWR r lie below M + kWrapRows
+                    const T* w = DUP ? (Wd + (((row0 & MASK) << LOGM) + col) * 2 + r * (ROWR * M * 2))
                                      : (Wd + ((((row0 + ROWR * r) & MASK) << LOGM) + col) * 2);
                     wr[e] = w[0];
                     wi[e] = w[1];
@@ -738,7 +753,7 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
 // WIDE: the launch holds M = 64 blocks (the shared area is sized for them and
 // each block branches on its window size).
 template <int NW, int PREC, bool WIDE>
-__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 3 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
+__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 4 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SharedHead& H = *reinterpret_cast<SharedHead*>(smem_raw);
     double* buf = reinterpret_cast<double*>(smem_raw + sizeof(SharedHead));

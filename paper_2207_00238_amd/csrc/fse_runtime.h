@@ -14,11 +14,14 @@
 
 namespace fse {
 
-// A grow-only device allocation.
+// A grow-only device allocation.  Growing retires the old allocation to
+// `retired` (freed later, where waiting for the device is acceptable):
+// hipFree waits for every stream of the device, which would stall this
+// call behind launches of other streams.
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
-    hipError_t ensure(size_t n);
+    hipError_t ensure(size_t n, std::vector<void*>& retired);
     void release();
 };
 
@@ -32,6 +35,8 @@ struct Workspace {
     size_t host_mask_cap = 0;
     uint8_t* stage = nullptr;  // pinned staging for the planning tables
     size_t stage_cap = 0;
+    // allocations replaced by larger ones, freed by free_all (device, pinned)
+    std::vector<void*> retired_dev, retired_host;
     hipStream_t last_stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // bracket the block kernel(s) of the last call
     bool timed = false;

@@ -213,9 +213,20 @@ fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** serv
         return FSE_ERR_DEVICE;
     }
     S->slots.resize(cfg->max_slots);
+    // Slot streams with a CU mask (all CUs): such a stream is given a hardware
+    // queue of its own, while plain streams share the runtime's small queue
+    // pool with every other stream of the process -- two slots on one queue
+    // would run their launches one after the other.
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    std::vector<uint32_t> cu_mask((size_t)std::max(1, (cus + 31) / 32), 0xffffffffu);
     for (auto& sl : S->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess) {
+        if (hipExtStreamCreateWithCUMask(&sl.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess) {
+            sl.stream = nullptr;
+            (void)hipGetLastError();
+            if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) sl.stream = nullptr;
+        }
+        if (!sl.stream || hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess) {
             for (auto& s2 : S->slots) {
                 if (s2.stream) (void)hipStreamDestroy(s2.stream);
                 if (s2.done_ev) (void)hipEventDestroy(s2.done_ev);

@@ -141,6 +141,10 @@ def main():
     ap.add_argument("--no-border-sweep", action="store_true",
                     help="skip the tile-border sweep (PSNR vs stripe width d at N = 32 tiles)")
     ap.add_argument("--serve-rate", type=float, default=16.0, help="requests per second of the served stream")
+    ap.add_argument("--serve-mixed-seconds", type=float, default=2.0,
+                    help="arrival window of the mixed-size served stream (0 = skip)")
+    ap.add_argument("--serve-mixed-rate", type=float, default=200.0,
+                    help="requests per second of the mixed-size served stream (sides 512..4096)")
     ap.add_argument("--only-batched", action="store_true",
                     help="measure the batched step only (for profiler runs): no secondary measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -366,6 +370,10 @@ def main():
         result["served"] = serve_stream(fse, torch, np, imgs, msks, p_serve, args.serve_rate, args.serve_seconds,
                                         nb1, res_single)
 
+    if args.serve_mixed_seconds > 0:
+        result["served_mixed"] = serve_mixed(fse, torch, np, common, args.serve_mixed_rate,
+                                             args.serve_mixed_seconds)
+
     if not args.no_plain:
         p_plain = fse.fse_params_default(schedule=fse.FSE_SCHED_PER_BLOCK, **common)
         torch.cuda.synchronize()
@@ -536,6 +544,55 @@ def serve_stream(fse, torch, np, imgs, msks, params, rate, seconds, blocks_per_r
             "value": blocks / (t_end - t0), "unit": "blocks/s",
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "bitwise_equal_to_alone": bool(torch.equal(outs[first0], ref0))}
+
+
+def serve_mixed(fse, torch, np, common, rate, seconds):
+    """Poisson arrivals of square requests with sides {512, 1024, 2048, 4096}
+    and two mask kinds (the serving trace of the input recipe) into the
+    server, at a rate above what the device can absorb: the achieved rate is
+    the saturation throughput and the latencies are queue-dominated.  Inputs
+    come from a pool of one image and mask per (side, kind)."""
+    from paper_2207_00238_amd import synth
+    dev = torch.device("cuda:0")
+    trace = synth.poisson_trace(rate, seconds, seed=31)
+    pool = {}
+    for req in trace:
+        key = (req["side"], req["kind"])
+        if key not in pool:
+            img, msk = synth.request_inputs(req)
+            pool[key] = (torch.from_numpy(img).to(dev), torch.from_numpy(msk).to(dev))
+    p = fse.fse_params_default(**{**common, "workgroups": 0})
+    outs = [torch.empty_like(pool[(r["side"], r["kind"])][0]) for r in trace]
+    torch.cuda.synchronize()
+    srv = fse.fse_serve_create(hbm_budget_bytes=32 << 30, max_slots=4)
+    tickets = []
+    try:
+        t0 = time.perf_counter()
+        for i, req in enumerate(trace):
+            now = time.perf_counter() - t0
+            if req["t"] > now:
+                time.sleep(req["t"] - now)
+            im, mk = pool[(req["side"], req["kind"])]
+            tickets.append(fse.fse_serve_submit(srv, im, mk, p, outs[i]))
+        stats = [fse.fse_serve_wait(srv, tk, 600_000_000) for tk in tickets]
+        t_end = time.perf_counter()
+    finally:
+        fse.fse_serve_destroy(srv)
+    lat = np.array([s["t_done_ms"] - s["t_submit_ms"] for s in stats])
+    blocks = sum(s["n_blocks"] for s in stats)
+    # one request of each side against the same request alone
+    same = True
+    for side in sorted({r["side"] for r in trace}):
+        i = next(k for k, r in enumerate(trace) if r["side"] == side)
+        im, mk = pool[(trace[i]["side"], trace[i]["kind"])]
+        o = torch.empty_like(im)
+        fse.fse_extrapolate(im, mk, p, o)
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(o, outs[i]))
+    return {"requests": len(trace), "rate_hz": rate, "seconds": seconds, "sides": [512, 1024, 2048, 4096],
+            "offered_blocks_per_s": blocks / seconds, "value": blocks / (t_end - t0), "unit": "blocks/s",
+            "drain_s": t_end - t0, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "bitwise_equal_to_alone": same}
 
 
 if __name__ == "__main__":

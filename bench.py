@@ -64,7 +64,7 @@ def traffic_from_profiles(workload: str, n_launch_units: float):
 
 
 def cpu_baseline():
-    """The FP64 oracle, single thread, on the top-left 640x480 crop of the
+    """The FP64 oracle, single thread, on the top-left 1280x720 crop of the
     workload's first image and mask (the crop is processed as an image of its
     own)."""
     import numpy as np
@@ -73,7 +73,7 @@ def cpu_baseline():
     from paper_2207_00238_amd import synth
 
     wl = synth.workload("hd")
-    crop = (480, 640)
+    crop = (720, 1280)
     img = wl.image[:crop[0], :crop[1]]
     msk = wl.mask[:crop[0], :crop[1]]
     nb = len(oracle.plan(msk, wl.classes)[0])

@@ -73,6 +73,19 @@ Workspace* workspace_for(hipStream_t st) {
     return slot.get();
 }
 
+void release_workspace(int dev, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, st});
+    if (it == g_ws.end()) return;
+    if (g_last_ws == it->second.get()) g_last_ws = nullptr;
+    {
+        std::lock_guard<std::mutex> wl(it->second->mu);
+        hipStreamSynchronize(st);
+        it->second->free_all();
+    }
+    g_ws.erase(it);
+}
+
 void release_all_workspaces() {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     g_last_ws = nullptr;

@@ -70,6 +70,8 @@ fse_status_t launch_prepared(Workspace& ws, Prepared& P, hipStream_t st, bool ti
 // statistics of this thread's last call as planned on the host (no device wait)
 void fse_last_stats_nowait(fse_run_stats_t* st);
 Workspace* workspace_for(hipStream_t st);
+// free the workspace of one stream (before the stream is destroyed)
+void release_workspace(int dev, hipStream_t st);
 void release_all_workspaces();
 int persistent_grid(int nw, int prec, bool wide);  // resident workgroups of the block kernel on the current device
 

@@ -206,6 +206,14 @@ fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** serv
         return FSE_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return FSE_ERR_INVALID_ARG;
+    // the streams are created on the server's device; the caller's current
+    // device is restored on return
+    int prev_dev = 0;
+    (void)hipGetDevice(&prev_dev);
+    struct RestoreDevice {
+        int d;
+        ~RestoreDevice() { (void)hipSetDevice(d); }
+    } restore{prev_dev};
     auto* S = new fse_server();
     S->cfg = *cfg;
     if (hipSetDevice(cfg->device) != hipSuccess) {
@@ -315,11 +323,16 @@ fse_status_t fse_serve_destroy(fse_server_t* S) {
         S->cv.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
+    int prev_dev = 0;
+    (void)hipGetDevice(&prev_dev);
+    (void)hipSetDevice(S->cfg.device);
     for (auto& sl : S->slots) {
         (void)hipStreamSynchronize(sl.stream);
+        release_workspace(S->cfg.device, sl.stream);  // the slot's device tables and staging
         (void)hipStreamDestroy(sl.stream);
         (void)hipEventDestroy(sl.done_ev);
     }
+    (void)hipSetDevice(prev_dev);
     delete S;
     return FSE_OK;
 }

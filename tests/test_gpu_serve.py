@@ -82,3 +82,33 @@ def test_budget_queues_and_rejects():
         assert ei.value.status == fse.FSE_ERR_BUDGET
     finally:
         fse.fse_serve_destroy(srv)
+
+
+def test_destroy_frees_slot_workspaces():
+    # each slot's device tables (128 MiB of FP64 reconstructed values alone
+    # for a 4096x4096 request) go back to the device when the server is destroyed
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    img, mask = _inputs(4096, 4096, 81, "blocks")
+    ti = torch.from_numpy(img).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    outs = [torch.empty_like(ti) for _ in range(3)]
+    p = fse.fse_params_default(classes=((4, 14, 10),))
+
+    def cycle():
+        srv = fse.fse_serve_create(hbm_budget_bytes=1 << 30, max_slots=3)
+        try:
+            tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for o in outs]
+            for t in tickets:
+                fse.fse_serve_wait(srv, t, 60_000_000)
+        finally:
+            fse.fse_serve_destroy(srv)
+        torch.cuda.synchronize()
+
+    cycle()  # first use: runtime state that stays for the process
+    free0 = torch.cuda.mem_get_info()[0]
+    cycle()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free0 - free1 < 64 << 20, f"{(free0 - free1) >> 20} MiB not returned"
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])

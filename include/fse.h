@@ -198,7 +198,10 @@ fse_status_t fse_last_stats(fse_run_stats_t* st);
 fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
                           fse_image_t* outs, void* stream, fse_params_t* best);
 
-/* Free all cached device workspace (waits for the streams that use it). */
+/* Free all cached device workspace (waits for the streams that use it).
+ * Calls running on other threads finish first (each holds its workspace's
+ * lock); fse_last_stats for a call whose workspace was freed returns the
+ * host-side statistics only (no kernel time, no device error flag). */
 fse_status_t fse_release(void);
 
 /* ---- prepared plans replayed as HIP graphs ---------------------------- */

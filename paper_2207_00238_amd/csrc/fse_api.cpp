@@ -21,7 +21,14 @@
 namespace fse {
 
 thread_local fse_run_stats_t g_last_stats{};
-thread_local Workspace* g_last_ws = nullptr;
+// the workspace of this thread's last call, by registry key and generation
+// (a released workspace is then recognised instead of dereferenced)
+struct LastCall {
+    int dev = -1;
+    hipStream_t st = nullptr;
+    uint64_t gen = 0;
+};
+thread_local LastCall g_last;
 
 static double now_ms() {
     using namespace std::chrono;
@@ -61,23 +68,28 @@ void DevBuf::release() {
 // ---------------------------------------------------------------------------
 // workspaces: one per (device, stream); calls on one stream are serialised
 // ---------------------------------------------------------------------------
+// Lock order: the registry mutex, then a workspace's mutex.
 static std::mutex g_ws_mu;
 static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+static uint64_t g_ws_gen = 0;  // under g_ws_mu
 
-Workspace* workspace_for(hipStream_t st) {
+Workspace* workspace_for(hipStream_t st, std::unique_lock<std::mutex>& lk) {
     int dev = 0;
     hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(g_ws_mu);
+    std::lock_guard<std::mutex> rl(g_ws_mu);
     auto& slot = g_ws[{dev, st}];
-    if (!slot) slot.reset(new Workspace());
+    if (!slot) {
+        slot.reset(new Workspace());
+        slot->gen = ++g_ws_gen;
+    }
+    lk = std::unique_lock<std::mutex>(slot->mu);
     return slot.get();
 }
 
 void release_workspace(int dev, hipStream_t st) {
-    std::lock_guard<std::mutex> lk(g_ws_mu);
+    std::lock_guard<std::mutex> rl(g_ws_mu);
     auto it = g_ws.find({dev, st});
     if (it == g_ws.end()) return;
-    if (g_last_ws == it->second.get()) g_last_ws = nullptr;
     {
         std::lock_guard<std::mutex> wl(it->second->mu);
         hipStreamSynchronize(st);
@@ -87,8 +99,7 @@ void release_workspace(int dev, hipStream_t st) {
 }
 
 void release_all_workspaces() {
-    std::lock_guard<std::mutex> lk(g_ws_mu);
-    g_last_ws = nullptr;
+    std::lock_guard<std::mutex> rl(g_ws_mu);
     for (auto& kv : g_ws) {
         std::lock_guard<std::mutex> wl(kv.second->mu);
         hipStreamSynchronize(kv.first.second);
@@ -263,9 +274,8 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     std::vector<ClassCfg> cls;
     fse_status_t s = check_batch(n, images, masks, p, outs, cls);
     if (s != FSE_OK) return s;
-    Workspace* wsp = workspace_for(st);
-    std::lock_guard<std::mutex> lk(wsp->mu);
-    Workspace& ws = *wsp;
+    std::unique_lock<std::mutex> lk;
+    Workspace& ws = *workspace_for(st, lk);
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return from_hip(e);
     Prepared P;
@@ -273,7 +283,9 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     if ((s = launch_prepared(ws, P, st, true)) != FSE_OK) return s;
     ws.last_stream = st;
     g_last_stats = P.stats;
-    g_last_ws = &ws;
+    int dev = 0;
+    hipGetDevice(&dev);
+    g_last = LastCall{dev, st, ws.gen};
     return FSE_OK;
 }
 
@@ -693,9 +705,18 @@ fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const f
 
 fse_status_t fse_last_stats(fse_run_stats_t* st) {
     if (!st) return FSE_ERR_INVALID_ARG;
-    Workspace* ws = g_last_ws;
+    // the last call's workspace, if it still exists (fse_release frees it)
+    Workspace* ws = nullptr;
+    std::unique_lock<std::mutex> lk;
+    if (g_last.gen) {
+        std::lock_guard<std::mutex> rl(g_ws_mu);
+        auto it = g_ws.find({g_last.dev, g_last.st});
+        if (it != g_ws.end() && it->second->gen == g_last.gen) {
+            ws = it->second.get();
+            lk = std::unique_lock<std::mutex>(ws->mu);
+        }
+    }
     if (ws) {
-        std::lock_guard<std::mutex> lk(ws->mu);
         hipError_t e = hipStreamSynchronize(ws->last_stream);
         if (e != hipSuccess) return from_hip(e);
         if (ws->timed) {

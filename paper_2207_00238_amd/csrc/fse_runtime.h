@@ -29,6 +29,7 @@ struct DevBuf {
 // same stream share one workspace and are serialised by its mutex.
 struct Workspace {
     std::mutex mu;
+    uint64_t gen = 0;  // registry generation: tells a released workspace from a new one on the same stream
     DevBuf recon, owner, desc, lbox, done, tickets, jobs, misc, tabs;
     std::vector<double> tab_key;  // parameters the uploaded tables were built for
     uint8_t* host_mask = nullptr;  // pinned staging for mask read-back
@@ -69,7 +70,10 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
 fse_status_t launch_prepared(Workspace& ws, Prepared& P, hipStream_t st, bool timed);
 // statistics of this thread's last call as planned on the host (no device wait)
 void fse_last_stats_nowait(fse_run_stats_t* st);
-Workspace* workspace_for(hipStream_t st);
+// The stream's workspace on the current device, returned with its mutex
+// held by `lk` (taken while the registry is locked, so a concurrent release
+// cannot free it in between).
+Workspace* workspace_for(hipStream_t st, std::unique_lock<std::mutex>& lk);
 // free the workspace of one stream (before the stream is destroyed)
 void release_workspace(int dev, hipStream_t st);
 void release_all_workspaces();

@@ -251,3 +251,18 @@ def test_tiled_small_stripes_match_tile_oracle(d):
     m = mask.astype(bool)
     assert np.array_equal(got[~m], img[~m])
     assert np.abs(got - ref)[m].max() <= TIGHT
+
+
+def test_release_then_reuse():
+    # fse_release frees the workspaces; the last call's statistics stay
+    # readable (host-side part) and the next call builds a new workspace
+    import torch
+    from paper_2207_00238_amd import fse
+    wl = synth.workload("small")
+    a, _, st_a = _run(wl.image, wl.mask, wl.classes)
+    fse.fse_release()
+    st = fse.fse_last_stats()
+    assert st["n_blocks"] == st_a["n_blocks"] and st["n_jobs"] == 1
+    b, _, st_b = _run(wl.image, wl.mask, wl.classes)
+    assert np.array_equal(a, b)
+    assert st_b["kernel_ms"] > 0

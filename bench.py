@@ -130,8 +130,9 @@ def main():
                     help="3840x2160 mixed-loss images for the tiled batch measurement (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-block comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--streams", type=int, default=3,
-                    help="streams the timed batched steps rotate over (1 = one step at a time)")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="streams the timed batched steps rotate over (1 = one step at a time; with the "
+                         "default four, plain streams still get hardware queues of their own)")
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--block-waves", type=int, default=4)
     ap.add_argument("--tiles", type=str, default="64",

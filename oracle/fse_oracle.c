@@ -16,7 +16,7 @@
  * (the orthogonality-deficiency compensation).  The paper gives the method in
  * prose only; the formulas below follow the standard form of the complex FSE
  * and every reading that the paper leaves open is listed in the design notes
- * as R1..R13.
+ * as R1..R16.
  *
  * Notation (window of M x M pixels, m = row, n = column, 0-based):
  *   w[m,n]   weight: rho^dist for known pixels, delta*rho^dist for pixels

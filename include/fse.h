@@ -136,7 +136,9 @@ typedef struct {
     int32_t wavefront_keys;
     double host_plan_ms;  /* host-side planning time */
     double kernel_ms;     /* device time of the block kernel(s), HIP events on the call's stream */
-    int32_t device_error; /* non-zero: a dependency wait hit its time limit (results invalid) */
+    int32_t device_error; /* non-zero: a dependency wait hit its time limit (results invalid); the limit is
+                             5 s, or FSE_WAIT_LIMIT_US microseconds from the environment when the launch is
+                             prepared */
 } fse_run_stats_t;
 
 const char* fse_status_string(fse_status_t s);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -289,6 +290,20 @@ fse_status_t run_batch(int n, const fse_image_t* images, const fse_mask_t* masks
     return FSE_OK;
 }
 
+// Bound of every dependency wait, in s_memrealtime ticks (100 MHz): 5 s, or
+// FSE_WAIT_LIMIT_US microseconds from the environment (read when a launch is
+// prepared).  A wait that reaches it sets the launch's error flag and goes
+// on, so a lost wake-up ends as an error instead of a hang.
+static int64_t wait_limit_ticks() {
+    int64_t us = 5000000;
+    if (const char* e = std::getenv("FSE_WAIT_LIMIT_US")) {
+        char* end = nullptr;
+        const long long v = std::strtoll(e, &end, 10);
+        if (end != e && v >= 0) us = v;
+    }
+    return us * 100;
+}
+
 fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, const fse_mask_t* masks,
                            const fse_params_t* p, const fse_image_t* outs, const std::vector<ClassCfg>& cls,
                            hipStream_t st, Prepared& P) {
@@ -514,7 +529,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     a.reach = reach;
     a.gamma = p->gamma;
     a.delta = p->recon_weight;
-    a.wait_limit = (int64_t)5 * 100000000;  // 5 s at 100 MHz
+    a.wait_limit = wait_limit_ticks();
     stats.host_plan_ms = now_ms() - t0;
 
     int max_w = 1, max_h = 1;

@@ -266,3 +266,21 @@ def test_release_then_reuse():
     b, _, st_b = _run(wl.image, wl.mask, wl.classes)
     assert np.array_equal(a, b)
     assert st_b["kernel_ms"] > 0
+
+
+def test_wait_limit_turns_into_an_error_flag(monkeypatch):
+    # a dependency wait that reaches its bound (forced tiny from the host)
+    # sets the launch's error flag; every block still finishes, and the next
+    # launch with the normal bound is clean and matches the oracle
+    img = synth.synth_image(256, 192, seed=91, period_max=128.0)
+    mask = synth.mask_blocks_and_pixels(256, 192, 4, 0.25, 0.01, seed=92)
+    cls = ((4, 14, 30),)
+    monkeypatch.setenv("FSE_WAIT_LIMIT_US", "0")
+    _, _, st = _run(img, mask, cls, workgroups=256)
+    assert st["device_error"] != 0
+    monkeypatch.delenv("FSE_WAIT_LIMIT_US")
+    got, _, st2 = _run(img, mask, cls, workgroups=256)
+    assert st2["device_error"] == 0
+    ref = O.image(img, mask, cls)
+    m = mask.astype(bool)
+    assert np.abs(got - ref)[m].max() <= TIGHT

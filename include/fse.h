@@ -242,8 +242,10 @@ typedef struct {
 
 fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** server);
 /* Queue a request.  The buffers are device pointers owned by the caller and
- * must stay valid until the request is done.  BUDGET when the request can
- * never fit the budget. */
+ * must stay valid until the request is done.  The server's streams are not
+ * ordered after the caller's: image and mask must hold their final contents
+ * when the request is submitted (synchronise the work that wrote them first).
+ * BUDGET when the request can never fit the budget. */
 fse_status_t fse_serve_submit(fse_server_t* s, const fse_image_t* image, const fse_mask_t* mask,
                               const fse_params_t* p, fse_image_t* out, uint64_t* ticket);
 fse_status_t fse_serve_poll(fse_server_t* s, uint64_t ticket, int32_t* done, fse_request_stats_t* st);

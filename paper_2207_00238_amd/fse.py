@@ -246,7 +246,9 @@ def fse_serve_create(hbm_budget_bytes: int, max_slots: int = 4, device: int = 0,
 
 
 def fse_serve_submit(server, image, mask, params: fse_params_t, out) -> int:
-    """Queue one request; the tensors must stay alive until it is done."""
+    """Queue one request.  The tensors must stay alive until it is done, and
+    image and mask must already hold their final contents: the server's
+    streams are not ordered after the caller's (synchronise first)."""
     im, mk, ot = _image(image), _mask(mask), _image(out)
     t = ctypes.c_uint64()
     check(lib().fse_serve_submit(server, ctypes.byref(im), ctypes.byref(mk), ctypes.byref(params), ctypes.byref(ot),

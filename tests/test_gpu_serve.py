@@ -62,6 +62,7 @@ def test_budget_queues_and_rejects():
     img, mask = _inputs(256, 256, 81, "blocks")
     ti = torch.from_numpy(img).to(dev)
     tm = torch.from_numpy(mask).to(dev)
+    torch.cuda.synchronize()  # inputs complete before the server's streams read them
     # budget fits about one request at a time: the rest must queue, not fail
     srv = fse.fse_serve_create(hbm_budget_bytes=256 * 256 * 14, max_slots=2)
     try:
@@ -94,6 +95,7 @@ def test_destroy_frees_slot_workspaces():
     ti = torch.from_numpy(img).to(dev)
     tm = torch.from_numpy(mask).to(dev)
     outs = [torch.empty_like(ti) for _ in range(3)]
+    torch.cuda.synchronize()  # inputs complete before the server's streams read them
     p = fse.fse_params_default(classes=((4, 14, 10),))
 
     def cycle():

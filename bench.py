@@ -146,6 +146,8 @@ def main():
                     help="arrival window of the mixed-size served stream (0 = skip)")
     ap.add_argument("--serve-mixed-rate", type=float, default=200.0,
                     help="requests per second of the mixed-size served stream (sides 512..4096)")
+    ap.add_argument("--only-uhd", action="store_true",
+                    help="measure only the 3840x2160 tiled batch, automatic grid, no autotuning (for profiler runs)")
     ap.add_argument("--only-batched", action="store_true",
                     help="measure the batched step only (for profiler runs): no secondary measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -171,6 +173,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    if args.only_uhd:
+        print(json.dumps({"uhd_tiled_batch": uhd_plain(fse, torch, np, max(1, args.uhd_images), args.steps,
+                                                       args.warmup)}), flush=True)
+        return
 
     n_img = max(1, args.batch)
     wls = [synth.workload("hd", i) for i in range(n_img)]
@@ -419,6 +426,28 @@ def border_sweep(fse, torch, np, img, msk, common, wl, p_whole):
     # grid of eq. (5): the overlap the compact tiling is there to avoid
     vert = [run(fse.FSE_TILED_VERTICAL, d) for d in (0, 8, 32)]
     return {"n_tiles": 32, "align": 4, "rows": rows, "vertical_stripes": vert}
+
+
+def uhd_plain(fse, torch, np, n, steps, warmup):
+    """The 3840x2160 tiled batch of :func:`uhd_batch` launched eagerly with the
+    automatic grid and no autotuning: a fixed launch sequence for profilers."""
+    from paper_2207_00238_amd import synth
+    dev = torch.device("cuda:0")
+    wls = [synth.workload("uhd", i) for i in range(n)]
+    imgs = [torch.from_numpy(w.image).to(dev) for w in wls]
+    msks = [torch.from_numpy(w.mask).to(dev) for w in wls]
+    outs = [torch.empty_like(t) for t in imgs]
+    p = fse.fse_params_default(classes=wls[0].classes, tiling=fse.FSE_TILED, n_tiles=64, overlap=32, align=16)
+    for _ in range(max(warmup, 1)):
+        fse.fse_extrapolate_batch(imgs, msks, p, outs)
+        fse.fse_last_stats()
+    kms = []
+    for _ in range(steps):
+        fse.fse_extrapolate_batch(imgs, msks, p, outs)
+        s = fse.fse_last_stats()
+        kms.append(s["kernel_ms"])
+    return {"images": n, "blocks_executed": s["n_blocks"], "kernel_ms": float(np.mean(kms)),
+            "value": s["n_blocks"] / (float(np.mean(kms)) / 1e3), "unit": "blocks/s (executed, kernel time)"}
 
 
 def uhd_batch(fse, torch, np, n, steps):

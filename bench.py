@@ -10,11 +10,16 @@ A step is one batched extrapolation of ``--batch`` requests on inputs already
 resident in HBM: host planning of every request's blocks and dependency
 order, upload of the plan, and one persistent dependency-driven kernel that
 runs the blocks of all requests.  ``value`` = processing blocks per second
-over the timed steps.  Also reported: one request alone, the paper's tile
-framework on one request, a served Poisson stream of requests (continuous
-batching, p50/p99 latency), the plain GPU path (one kernel launch per block,
-raster order; bitwise-identical output), and the FP64 CPU oracle on a
-bounded sample.
+over the timed steps, which rotate over ``--streams`` streams (default four)
+so that the host planning of one batch and the launches of the batches
+before it overlap; the outputs are checked bitwise against steps run one at
+a time.  The roofline, the kernel time and the step latencies come from
+those one-at-a-time steps (a launch alone on the device).  Also reported:
+one request alone, the paper's tile framework on one request, the tile-border
+and tiling comparisons, the 3840x2160 tiled batch, FP32 and BF16x3 against
+FP64, served Poisson streams (continuous batching, p50/p99 latency), the
+plain GPU path (one kernel launch per block, raster order; bitwise-identical
+output), and the FP64 CPU oracle on a bounded sample.
 
 Prints one JSON line.
 """

@@ -1,18 +1,23 @@
 // fse_kernels.hip -- gfx950 kernels of Frequency Selective Extrapolation.
 //
-// One processing block per 256-thread workgroup (four wave64).  Per block:
-//   1. wait until every earlier block that shares pixels with this block's
+// One processing block per workgroup of one, two or four wave64 (eight in
+// launches with 64 x 64 windows).  Per block:
+//   1. stage the M x M support window from the mask, the plan and the image:
+//      weights w = rho^dist (known pixels), delta rho^dist (pixels owned by an
+//      earlier block, reconstructed by the time this one runs in raster
+//      order), 0 (lost or outside); W0 = sum w; the known part of w*s; and
+//      the DFT of w -- all of it fixed before any earlier block finishes;
+//   2. wait until every earlier block that shares pixels with this block's
 //      support window (in either direction) has finished, so the window holds
 //      exactly what a strict raster-order pass would see;
-//   2. stage the M x M support window: weights w = rho^dist (known pixels),
-//      delta rho^dist (reconstructed pixels), 0 (lost or outside); W0 = sum w;
-//   3. weighted forward 2-D DFT of w*s and of w as F X F on the FP64 matrix
-//      cores (v_mfma_f64_16x16x4f64), F[k,m] = e^{-2 pi i k m / M};
+//   3. add the reconstructed values to w*s and take its DFT; both DFTs are
+//      F X F on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
+//      F[k,m] = e^{-2 pi i k m / M};
 //   4. K greedy steps: argmax of |R|^2 (ties to the smallest index),
 //      alpha = gamma R[u,v] / W0, R -= alpha * W shifted by (u,v);
 //   5. evaluate Re sum alpha e^{+2 pi i (u m + v n)/M} at the block's lost
 //      pixels, store them (FP64 working copy and float32 output), publish.
-// The block model is Sec. II of the paper; steps 1 and the persistent
+// The block model is Sec. II of the paper; the wait and the persistent
 // ticket dispatch are this library's way of running it on the GPU.
 #include <hip/hip_runtime.h>
 

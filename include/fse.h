@@ -49,6 +49,7 @@ typedef int32_t fse_status_t;
 #define FSE_ERR_TIMEOUT (-6)
 #define FSE_ERR_NOT_FOUND (-7)
 #define FSE_ERR_BUSY (-8)
+#define FSE_ERR_CANCELLED (-9)
 
 /* arithmetic of the DFT and of the selection loop */
 #define FSE_PREC_F64 0   /* FP64 MFMA DFT, FP64 loop, FP64 reconstructed values */
@@ -251,6 +252,11 @@ fse_status_t fse_serve_submit(fse_server_t* s, const fse_image_t* image, const f
 fse_status_t fse_serve_poll(fse_server_t* s, uint64_t ticket, int32_t* done, fse_request_stats_t* st);
 /* timeout_us < 0 waits without limit; TIMEOUT when it expires. */
 fse_status_t fse_serve_wait(fse_server_t* s, uint64_t ticket, int64_t timeout_us, fse_request_stats_t* st);
+/* Withdraw a request that is still queued: its wait and poll then report
+ * CANCELLED and its output is left untouched.  BUSY once it has been admitted
+ * into a launch (it then completes normally); NOT_FOUND for an unknown or
+ * already collected ticket. */
+fse_status_t fse_serve_cancel(fse_server_t* s, uint64_t ticket);
 fse_status_t fse_serve_destroy(fse_server_t* s);
 
 #ifdef __cplusplus

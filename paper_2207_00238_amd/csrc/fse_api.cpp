@@ -639,6 +639,7 @@ const char* fse_status_string(fse_status_t s) {
         case FSE_ERR_TIMEOUT: return "timed out";
         case FSE_ERR_NOT_FOUND: return "unknown ticket";
         case FSE_ERR_BUSY: return "busy";
+        case FSE_ERR_CANCELLED: return "cancelled";
         default: return "unknown status";
     }
 }

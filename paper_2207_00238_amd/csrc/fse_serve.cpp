@@ -315,6 +315,21 @@ fse_status_t fse_serve_wait(fse_server_t* S, uint64_t ticket, int64_t timeout_us
     return s;
 }
 
+fse_status_t fse_serve_cancel(fse_server_t* S, uint64_t ticket) {
+    if (!S) return FSE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
+    const std::shared_ptr<Request> r = it->second;
+    if (r->state != 0) return FSE_ERR_BUSY;  // admitted into a launch (or finished): it runs to the end
+    S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
+    r->state = 3;
+    r->status = FSE_ERR_CANCELLED;
+    r->t_done = steady_ms();
+    S->done_cv.notify_all();
+    return FSE_OK;
+}
+
 fse_status_t fse_serve_destroy(fse_server_t* S) {
     if (!S) return FSE_ERR_INVALID_ARG;
     {

@@ -22,6 +22,7 @@ FSE_ERR_DEVICE = -5
 FSE_ERR_TIMEOUT = -6
 FSE_ERR_NOT_FOUND = -7
 FSE_ERR_BUSY = -8
+FSE_ERR_CANCELLED = -9
 
 FSE_PREC_F64, FSE_PREC_F32, FSE_PREC_BF16X3 = 0, 1, 2
 FSE_SCHED_PERSISTENT, FSE_SCHED_WAVEFRONT, FSE_SCHED_PER_BLOCK = 0, 1, 2
@@ -32,7 +33,7 @@ EXPORTED = [
     "fse_status_string", "fse_params_default", "fse_plan_tiles", "fse_extrapolate", "fse_extrapolate_batch",
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
     "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy",
-    "fse_autotune", "fse_plan_tiles_vertical",
+    "fse_autotune", "fse_plan_tiles_vertical", "fse_serve_cancel",
 ]
 
 
@@ -121,6 +122,8 @@ def lib():
         L.fse_serve_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, P(ctypes.c_int32), P(fse_request_stats_t)]
         L.fse_serve_wait.restype = st
         L.fse_serve_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, P(fse_request_stats_t)]
+        L.fse_serve_cancel.restype = st
+        L.fse_serve_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
         L.fse_serve_destroy.restype = st
         L.fse_serve_destroy.argtypes = [ctypes.c_void_p]
         L.fse_autotune.restype = st
@@ -271,6 +274,17 @@ def fse_serve_wait(server, ticket: int, timeout_us: int = -1) -> dict:
     st = fse_request_stats_t()
     check(lib().fse_serve_wait(server, ticket, timeout_us, ctypes.byref(st)), "fse_serve_wait")
     return _req_stats(st)
+
+
+def fse_serve_cancel(server, ticket: int) -> bool:
+    """Withdraw a queued request: True when withdrawn (its wait then raises
+    with FSE_ERR_CANCELLED), False when it was already admitted into a launch
+    (it completes normally)."""
+    s = lib().fse_serve_cancel(server, ticket)
+    if s == FSE_ERR_BUSY:
+        return False
+    check(s, "fse_serve_cancel")
+    return True
 
 
 def fse_serve_destroy(server) -> None:

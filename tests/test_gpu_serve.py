@@ -114,3 +114,33 @@ def test_destroy_frees_slot_workspaces():
     free1 = torch.cuda.mem_get_info()[0]
     assert free0 - free1 < 64 << 20, f"{(free0 - free1) >> 20} MiB not returned"
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+def test_cancel_a_queued_request():
+    # the budget admits one 2048x2048 request at a time: of three submitted
+    # together, the third is still queued when it is withdrawn
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    img, mask = _inputs(2048, 2048, 85, "pixels")
+    ti = torch.from_numpy(img).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    outs = [torch.full_like(ti, -3.0) for _ in range(3)]
+    torch.cuda.synchronize()
+    p = fse.fse_params_default(classes=((4, 14, 30),))
+    srv = fse.fse_serve_create(hbm_budget_bytes=2048 * 2048 * 12, max_slots=2)
+    try:
+        tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for o in outs]
+        assert fse.fse_serve_cancel(srv, tickets[2])
+        with pytest.raises(fse.FseError) as ei:
+            fse.fse_serve_wait(srv, tickets[2], 60_000_000)
+        assert ei.value.status == fse.FSE_ERR_CANCELLED
+        for t in tickets[:2]:
+            fse.fse_serve_wait(srv, t, 60_000_000)
+        with pytest.raises(fse.FseError) as ei:  # collected tickets are gone
+            fse.fse_serve_cancel(srv, tickets[0])
+        assert ei.value.status == fse.FSE_ERR_NOT_FOUND
+    finally:
+        fse.fse_serve_destroy(srv)
+    assert torch.equal(outs[0], outs[1])
+    assert (outs[2] == -3.0).all()  # the withdrawn request never ran

@@ -50,6 +50,28 @@ def block_flops(M: int, K: int, B: int) -> float:
     return 24.0 * M ** 3 + K * M * M * 11.0 + B * B * K * 4.0
 
 
+def ssim(x, ref) -> float:
+    """Mean structural similarity of image x (clipped to [0, 255]) against ref
+    (Wang et al. 2004: Gaussian window of sigma 1.5 over 11 x 11 pixels,
+    K1 = 0.01, K2 = 0.03, L = 255), the paper's second quality measure."""
+    import numpy as np
+    from scipy.ndimage import gaussian_filter
+
+    a = np.clip(np.asarray(x, np.float64), 0, 255)
+    b = np.asarray(ref, np.float64)
+
+    def f(v):
+        return gaussian_filter(v, 1.5, truncate=3.5)
+
+    mu_a, mu_b = f(a), f(b)
+    s_aa = f(a * a) - mu_a * mu_a
+    s_bb = f(b * b) - mu_b * mu_b
+    s_ab = f(a * b) - mu_a * mu_b
+    c1, c2 = (0.01 * 255) ** 2, (0.03 * 255) ** 2
+    m = ((2 * mu_a * mu_b + c1) * (2 * s_ab + c2)) / ((mu_a * mu_a + mu_b * mu_b + c1) * (s_aa + s_bb + c2))
+    return float(m.mean())
+
+
 def kernel_source_hash() -> str:
     src = os.path.join(ROOT, "paper_2207_00238_amd", "csrc", "fse_kernels.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -360,7 +382,9 @@ def main():
             return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
 
         p_whole = psnr(res_single.cpu())
+        s_whole = ssim(res_single.cpu().numpy(), wl.image)
         result["psnr_whole_db"] = p_whole
+        result["ssim_whole"] = s_whole
         result["tiled"] = []
         for N in [int(v) for v in args.tiles.split(",") if v]:
             pt = fse.fse_params_default(tiling=fse.FSE_TILED, n_tiles=N, overlap=32, align=16, **common)
@@ -376,10 +400,11 @@ def main():
             result["tiled"].append({"n_tiles": N, "overlap": 32, "value": nb1 / dt, "unit": "blocks/s",
                                     "ms_per_step": dt * 1e3, "kernel_ms": s["kernel_ms"],
                                     "blocks_executed": s["n_blocks"],
-                                    "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole})
+                                    "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole,
+                                    "dssim_vs_whole": ssim(out.cpu().numpy(), wl.image) - s_whole})
 
     if args.tiles and not args.no_border_sweep:
-        result["tile_border_sweep"] = border_sweep(fse, torch, np, img, msk, common, wl, p_whole)
+        result["tile_border_sweep"] = border_sweep(fse, torch, np, img, msk, common, wl, p_whole, s_whole)
 
     if args.uhd_images > 0:
         result["uhd_tiled_batch"] = uhd_batch(fse, torch, np, args.uhd_images, args.steps)
@@ -418,13 +443,14 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def border_sweep(fse, torch, np, img, msk, common, wl, p_whole):
+def border_sweep(fse, torch, np, img, msk, common, wl, p_whole, s_whole):
     """The paper's tile-border experiment (Sec. IV, PSNR against the stripe
     width d) on the first 1080p request: N = 32 tiles of the compact tiling,
     stripes d in {0, 1, 2, 4, 8, ..., 96} (tile cores on the 4-pixel block grid), each
     tile extrapolated as an independent image, cropped and merged.  PSNR over
-    the lost pixels against the ground truth, its change against the
-    whole-image result, and the executed blocks (stripes add work)."""
+    the lost pixels against the ground truth and SSIM of the whole image, their
+    change against the whole-image result, and the executed blocks (stripes
+    add work)."""
     m = torch.from_numpy(wl.mask).bool()
     gt = torch.from_numpy(wl.image).double()
     out = torch.empty_like(img)
@@ -434,7 +460,8 @@ def border_sweep(fse, torch, np, img, msk, common, wl, p_whole):
         s = fse.fse_last_stats()
         e = (out.cpu().double().clamp(0, 255) - gt)[m]
         ps = float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
-        return {"d": d, "psnr_db": ps, "dpsnr_vs_whole_db": ps - p_whole, "blocks_executed": s["n_blocks"],
+        return {"d": d, "psnr_db": ps, "dpsnr_vs_whole_db": ps - p_whole,
+                "dssim_vs_whole": ssim(out.cpu().numpy(), wl.image) - s_whole, "blocks_executed": s["n_blocks"],
                 "kernel_ms": s["kernel_ms"]}
 
     rows = [run(fse.FSE_TILED, d) for d in (0, 1, 2, 4, 8, 16, 24, 32, 48, 64, 96)]

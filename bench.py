@@ -403,6 +403,19 @@ def main():
                                     "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole,
                                     "dssim_vs_whole": ssim(out.cpu().numpy(), wl.image) - s_whole})
 
+    # the time to compute a tiling (the paper times its tilings of 6024x4024
+    # images): fse_plan_tiles through a bare ctypes call, mean over repeated
+    # calls -- an upper bound, the call overhead included
+    lib = fse.lib()
+    tiles_buf = (fse.fse_tile_t * 64)()
+    result["tiling_time_us"] = {"note": "6024x4024, d = 32; one ctypes call, overhead included"}
+    for N in (16, 32, 64):
+        reps = 20000
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lib.fse_plan_tiles(6024, 4024, N, 32, 4, tiles_buf)
+        result["tiling_time_us"][str(N)] = (time.perf_counter() - t0) / reps * 1e6
+
     if args.tiles and not args.no_border_sweep:
         result["tile_border_sweep"] = border_sweep(fse, torch, np, img, msk, common, wl, p_whole, s_whole)
 

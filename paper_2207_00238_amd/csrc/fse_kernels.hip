@@ -34,34 +34,43 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // working-state initialisation
 // ---------------------------------------------------------------------------
-__global__ void k_init_job(const JobDev* __restrict__ jobs, int32_t* counter, int32_t* error,
+// grid: x over columns, y over rows (strided), z over the jobs job0 ..
+__global__ void k_init_job(const JobDev* __restrict__ jobs, int job0, int32_t* counter, int32_t* error,
                            int64_t* degenerate) {
-    const JobDev& J = jobs[blockIdx.z];
+    const JobDev& J = jobs[job0 + blockIdx.z];
     // clear the completion flags of this job's blocks
     const int64_t flat = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nflat = (int64_t)gridDim.x * gridDim.y * blockDim.x;
     for (int64_t i = flat; i < J.n_blocks; i += nflat) J.done[i] = 0;
-    if (flat == 0 && blockIdx.z == 0) {
+    if (flat == 0 && job0 + blockIdx.z == 0) {
         if (counter) *counter = 0;
         *error = 0;
         *degenerate = 0;
     }
-    const int y = blockIdx.y;
-    if (y >= J.H) return;
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < J.W; x += gridDim.x * blockDim.x) {
-        const int gy = J.oy + y, gx = J.ox + x;
-        const uint8_t lost = J.mask[(int64_t)gy * J.mask_pitch + gx] != 0;
-        if (!lost && y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
-            J.out[(int64_t)gy * J.out_pitch + gx] = J.img[(int64_t)gy * J.img_pitch + gx];
+    for (int y = blockIdx.y; y < J.H; y += gridDim.y) {
+        for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < J.W; x += gridDim.x * blockDim.x) {
+            const int gy = J.oy + y, gx = J.ox + x;
+            const uint8_t lost = J.mask[(int64_t)gy * J.mask_pitch + gx] != 0;
+            if (!lost && y >= J.cy0 && y < J.cy1 && x >= J.cx0 && x < J.cx1)
+                J.out[(int64_t)gy * J.out_pitch + gx] = J.img[(int64_t)gy * J.img_pitch + gx];
+        }
     }
 }
 
+// One launch per 65535 jobs (the grid's z limit); rows strided over at most
+// 4096 grid rows.  The launch holding job 0 also clears the shared counters.
 hipError_t launch_init_job(const JobDev* jobs_dev, int n_jobs, int max_w, int max_h, int32_t* counter,
                            int32_t* error, int64_t* degenerate, hipStream_t st) {
     if (n_jobs <= 0) return hipSuccess;
-    dim3 grid((max_w + 255) / 256, max_h, n_jobs);
-    hipLaunchKernelGGL(k_init_job, grid, dim3(256), 0, st, jobs_dev, counter, error, degenerate);
-    return hipGetLastError();
+    constexpr int kMaxZ = 65535, kMaxY = 4096;
+    for (int job0 = 0; job0 < n_jobs; job0 += kMaxZ) {
+        const int nz = std::min(kMaxZ, n_jobs - job0);
+        dim3 grid((max_w + 255) / 256, std::min(max_h, kMaxY), nz);
+        hipLaunchKernelGGL(k_init_job, grid, dim3(256), 0, st, jobs_dev, job0, counter, error, degenerate);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

@@ -284,3 +284,37 @@ def test_wait_limit_turns_into_an_error_flag(monkeypatch):
     ref = O.image(img, mask, cls)
     m = mask.astype(bool)
     assert np.abs(got - ref)[m].max() <= TIGHT
+
+
+def test_batch_with_more_jobs_than_one_grid_dimension():
+    # 17 images x 4096 tiles = 69632 jobs: the start-up kernel runs in chunks
+    # of at most 65535 jobs; results equal each image launched alone, and the
+    # first image equals the per-tile oracle
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    W = H = 1024
+    cls = ((4, 14, 12),)
+    imgs, msks, host = [], [], []
+    for i in range(17):
+        img = synth.synth_image(W, H, seed=700 + i)
+        mask = synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=800 + i)
+        host.append((img, mask))
+        imgs.append(torch.from_numpy(img).to(dev))
+        msks.append(torch.from_numpy(mask).to(dev))
+    outs = [torch.full_like(t, -5.0) for t in imgs]
+    p = fse.fse_params_default(classes=cls, tiling=fse.FSE_TILED, n_tiles=4096, overlap=0, align=4)
+    fse.fse_extrapolate_batch(imgs, msks, p, outs)
+    st = fse.fse_last_stats()
+    assert st["n_jobs"] == 17 * 4096 and st["device_error"] == 0
+    for i in (0, 16):
+        alone = torch.full_like(imgs[i], -6.0)
+        fse.fse_extrapolate(imgs[i], msks[i], p, alone)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, outs[i]), f"image {i}: batched differs from alone"
+    img, mask = host[0]
+    ref = O.image_tiled(img, mask, cls, 4096, 0, 4)
+    got = outs[0].cpu().numpy()
+    m = mask.astype(bool)
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT

@@ -318,3 +318,33 @@ def test_batch_with_more_jobs_than_one_grid_dimension():
     m = mask.astype(bool)
     assert np.array_equal(got[~m], img[~m])
     assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT
+
+
+@pytest.mark.parametrize("tiled", [False, True])
+def test_pitched_views(tiled):
+    # image, mask and output are column slices of wider buffers (three
+    # different pitches); pixels of the output buffer outside the view stay
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    W, H = 200, 136
+    img = synth.synth_image(W, H, seed=95, period_max=128.0)
+    mask = synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=96)
+    cls = ((4, 14, 40),)
+    ibuf = torch.full((H, 231), 7.0, dtype=torch.float32, device=dev)
+    mbuf = torch.zeros((H, 256), dtype=torch.uint8, device=dev)
+    obuf = torch.full((H, 217), -9.0, dtype=torch.float32, device=dev)
+    ti, tm, to = ibuf[:, 5:5 + W], mbuf[:, 40:40 + W], obuf[:, 11:11 + W]
+    ti.copy_(torch.from_numpy(img))
+    tm.copy_(torch.from_numpy(mask))
+    kw = dict(tiling=fse.FSE_TILED, n_tiles=6, overlap=32, align=4) if tiled else {}
+    p = fse.fse_params_default(classes=cls, **kw)
+    fse.fse_extrapolate(ti, tm, p, to)
+    torch.cuda.synchronize()
+    ref = O.image_tiled(img, mask, cls, 6, 32, 4) if tiled else O.image(img, mask, cls)
+    got = to.cpu().numpy()
+    m = mask.astype(bool)
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT
+    ob = obuf.cpu().numpy()
+    assert (ob[:, :11] == -9.0).all() and (ob[:, 11 + W:] == -9.0).all()

@@ -348,3 +348,44 @@ def test_pitched_views(tiled):
     assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT
     ob = obuf.cpu().numpy()
     assert (ob[:, :11] == -9.0).all() and (ob[:, 11 + W:] == -9.0).all()
+
+
+def test_ordered_after_the_callers_stream():
+    # image and mask are produced by device work on a side stream and handed
+    # to the library on that stream with no synchronisation in between: the
+    # library's mask read-back and launch follow that work.  The output then
+    # feeds another call on a second stream after an event wait.
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    W, H = 160, 120
+    img = synth.synth_image(W, H, seed=97, period_max=128.0)
+    mask = synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=98)
+    cls = ((4, 14, 40),)
+    h_img = torch.from_numpy(img).pin_memory()
+    h_mask = torch.from_numpy(mask).pin_memory()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    p = fse.fse_params_default(classes=cls)
+    with torch.cuda.stream(s1):
+        ti = torch.empty((H, W), dtype=torch.float32, device=dev)
+        tm = torch.empty((H, W), dtype=torch.uint8, device=dev)
+        a = torch.randn((2048, 2048), device=dev)
+        for _ in range(8):  # keep the stream busy so that unordered reads would see unwritten memory
+            a = a @ a * 1e-3
+        ti.copy_(h_img, non_blocking=True)
+        tm.copy_(h_mask, non_blocking=True)
+        out = torch.empty_like(ti)
+        fse.fse_extrapolate(ti, tm, p, out, s1)
+        done = torch.cuda.Event()
+        done.record(s1)
+    s2.wait_event(done)
+    with torch.cuda.stream(s2):
+        out2 = torch.empty_like(out)
+        fse.fse_extrapolate(out, tm, p, out2, s2)  # lost pixels of out are re-extrapolated from the same support
+    torch.cuda.synchronize()
+    ref = O.image(img, mask, cls)
+    m = mask.astype(bool)
+    got = out.cpu().numpy()
+    assert np.array_equal(got[~m], img[~m])
+    assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT
+    assert torch.equal(out2, out)

@@ -144,3 +144,32 @@ def test_cancel_a_queued_request():
         fse.fse_serve_destroy(srv)
     assert torch.equal(outs[0], outs[1])
     assert (outs[2] == -3.0).all()  # the withdrawn request never ran
+
+
+def test_mixed_parameters_in_one_server():
+    # requests with different parameters (K, tiling) never share a launch;
+    # each result equals the same request alone
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    pa = fse.fse_params_default(classes=((4, 14, 60),))
+    pb = fse.fse_params_default(classes=((4, 14, 20),))
+    pc = fse.fse_params_default(classes=((4, 14, 60),), tiling=fse.FSE_TILED, n_tiles=4, overlap=16, align=4)
+    cases = []
+    for i, p in enumerate([pa, pb, pc, pa, pb, pc]):
+        img, mask = _inputs(96 + 8 * i, 80, 101 + i, "pixels")
+        ti = torch.from_numpy(img).to(dev)
+        tm = torch.from_numpy(mask).to(dev)
+        alone = torch.empty_like(ti)
+        fse.fse_extrapolate(ti, tm, p, alone)
+        cases.append((ti, tm, p, alone, torch.full_like(ti, -1.0)))
+    torch.cuda.synchronize()
+    srv = fse.fse_serve_create(hbm_budget_bytes=1 << 30, max_slots=3)
+    try:
+        tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for (ti, tm, p, _, o) in cases]
+        for t in tickets:
+            fse.fse_serve_wait(srv, t, 60_000_000)
+    finally:
+        fse.fse_serve_destroy(srv)
+    for k, (_, _, _, alone, o) in enumerate(cases):
+        assert torch.equal(alone, o), f"request {k}: served differs from alone"

@@ -334,7 +334,10 @@ def main():
         "host_plan_ms": float(np.mean(plan_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": traffic,
-                     "kernel": f"k_fse_blocks<{params.block_waves}>", "flops_per_block": flops},
+                     "kernel": f"k_fse_blocks<{params.block_waves}>", "flops_per_block": flops,
+                     # the same work over the overlapped timed steps (launches share the device there)
+                     "achieved_overlapped": n_blocks * flops * args.steps / total / 1e12,
+                     "frac_overlapped": n_blocks * flops * args.steps / total / 1e12 / MI355X_FP64_VECTOR_TFLOPS},
     }
 
     if args.only_batched:

@@ -88,6 +88,21 @@ __device__ __forceinline__ T const_load(const T* p) {
 #endif
 }
 
+// Uniform loads of block-constant records (the job and block descriptors):
+// each dword passes through readfirstlane, so the record lives in SGPRs for
+// the whole block instead of occupying a VGPR per dword.  (The compiler
+// otherwise turns these loads into per-lane vector loads.)
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "dword records");
+    T r;
+    const int32_t* s = reinterpret_cast<const int32_t*>(p);
+    int32_t* d = reinterpret_cast<int32_t*>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(const_load(s + i));
+    return r;
+}
+
 // Completion flags are polled with relaxed loads; one acquire fence follows
 // the wait.  (An acquire load per poll would invalidate caches on every
 // iteration of the wait.)
@@ -110,9 +125,10 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
 // dependency wait until the DFT of w*s after it, followed by a region that
 // first holds w (M x (M+1)) and then the weight spectrum for the K steps
 // (M = 32: (32 + kWrapRows) x 32 complex, rows 0 .. kWrapRows-1 repeated
-// after row 31; M = 64: 64 x 64 complex).  The coefficient list lives in the
-// head.  Sized for M = 32 (38 KB with the head: four blocks fit in a CU's
-// 160 KB) or, when a launch has M = 64 blocks, for M = 64 (97 KB).
+// after row 31; M = 64: 64 x 64 complex).  The coefficient list of the K
+// steps takes the part of the area that the steps no longer read.  Sized for
+// M = 32 (32 KB with the head) or, when a launch has M = 64 blocks, for
+// M = 64 (97 KB).
 constexpr int kMaxK = 256;
 // A lane's four elements of one row tile lie on rows base + ROWR r (r < 4,
 // ROWR <= 4 rows): with the base reduced mod 32 they stay below 32 + 12.
@@ -122,7 +138,6 @@ constexpr int kBufDoubles64 = 64 * 65 + 64 * 64 * 2;      // w*s, then the weigh
 
 struct SharedHead {
     double twc32[32], tws32[32];
-    double twc64[64], tws64[64];
     double part[8];
     // per step (double-buffered) and wave: the wave winner's energy, spectrum
     // index and coefficient
@@ -130,19 +145,21 @@ struct SharedHead {
     double2 sA[2][8];
     int job, blk, wait_fail;
     uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
-    // coefficient list of the K steps (written during the steps, read by the
-    // synthesis)
-    double car[kMaxK], cai[kMaxK];
-    int32_t cidx[kMaxK];
 };
 
-template <int NBUF>
-struct SharedT {
+// 32 x 32 launches: the head and the buffer (32 KB in all, so the LDS of a CU
+// holds five blocks; the 128-VGPR bound of the FP64 kernel holds four).
+// Launches with 64 x 64 windows add the 64-point twiddles.
+struct Shared32 {
     SharedHead h;
-    double buf[NBUF];
+    double buf[kBufDoubles32];
 };
-using Shared32 = SharedT<kBufDoubles32>;
-using Shared64 = SharedT<kBufDoubles64>;
+struct Shared64 {
+    SharedHead h;
+    double tw64[128];  // cos, then sin, of 2 pi p / 64
+    double buf[kBufDoubles64];
+};
+static_assert(sizeof(Shared32) <= 32768, "five 32 x 32 blocks per CU");
 
 // Unsigned 32-bit maximum over a wave64 with DPP; the result is valid in
 // lane 63.  Non-negative doubles order like their bit patterns, so the high
@@ -337,7 +354,8 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
 // waves, all of which stage the window, wait and synthesise (waves past NW
 // only keep the barriers of the DFT and the K steps).
 template <int M, int NW, int NWG, int PREC>
-__device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& H, double* buf) {
+__device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& H, double* buf,
+                              const double* tw64) {
     using T = typename PrecType<PREC>::T;
     using acc4 = typename std::conditional<PREC == kPrecF64, dbl4, flt4>::type;
     using TM = TileMap<M, NW>;
@@ -353,14 +371,14 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     constexpr int MASK = M - 1;
     constexpr int LOGM = (M == 32) ? 5 : 6;
     constexpr bool DUP = (M == 32);           // weight spectrum rows 0 .. kWrapRows-1 repeated after row M-1
-    const double* twc = (M == 32) ? H.twc32 : H.twc64;
-    const double* tws = (M == 32) ? H.tws32 : H.tws64;
+    const double* twc = (M == 32) ? H.twc32 : tw64;
+    const double* tws = (M == 32) ? H.tws32 : tw64 + 64;
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wv = t >> 6;
     const bool active = wv < NW;  // wave-uniform
     const int ti0 = TM::ti0(wv), tj0 = TM::tj0(wv);
-    const int4 d = const_load(J.desc + blk);
+    const int4 d = uniform_load(J.desc + blk);
     const ClassDev& C = a.cls[d.z];
     const int B = C.B, b = C.b, K = C.K;
     const int wy = d.x - b, wx = d.y - b;  // window origin (region coords); desc = (y0, x0, cls, 0)
@@ -375,6 +393,18 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     T* Xs = reinterpret_cast<T*>(buf);  // w * s, [m][n] stride LD
     T* Wd = Xs + M * LD;                // weight spectrum [DUP ? M + kWrapRows : M][M] complex
     T* Xw = Wd;                         // w, staged where the weight spectrum goes
+    // coefficient list of the K steps (real parts, imaginary parts, spectrum
+    // indices), written during the steps and read by the synthesis: in FP64
+    // over w*s, which the steps no longer read; in FP32 after the weight
+    // spectrum, where the buffer (sized for FP64) is free
+    constexpr int kWdRows = DUP ? M + kWrapRows : M;
+    static_assert(F64 ? 2 * kMaxK + kMaxK / 2 <= M * LD
+                      : (M * LD + kWdRows * M * 2) / 2 + 2 * kMaxK + kMaxK / 2 <= (M == 32 ? kBufDoubles32 : kBufDoubles64),
+                  "coefficient list inside the buffer");
+    double* const clist = F64 ? buf : reinterpret_cast<double*>(Wd + kWdRows * M * 2);
+    double* const car = clist;
+    double* const cai = clist + kMaxK;
+    int32_t* const cidx = reinterpret_cast<int32_t*>(clist + 2 * kMaxK);
     const int Bm = a.Bmin;
     double wsum = 0.0;
     unsigned recon_bits = 0;  // this thread's pixels that hold reconstructed values
@@ -531,10 +561,14 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // from here on the block is ready work: its waves issue ahead of the
     // pre-wait staging of other blocks on the same SIMDs
     __builtin_amdgcn_s_setprio(3);
+    // the pixel coordinates again, opaque to the compiler: the addresses are
+    // recomputed here instead of being kept from the staging across the DFT
+    int tp = t;
+    asm volatile("" : "+v"(tp));
 #pragma unroll
     for (int j = 0; j < NPIX; ++j) {
         if (recon_bits >> j & 1) {
-            const int m = (t >> LOGM) + RS * j, n = t & MASK;
+            const int m = (tp >> LOGM) + RS * j, n = tp & MASK;
             const int64_t q = (int64_t)(wy + m) * J.W + (wx + n);
             Xs[m * LD + n] = (T)(a.delta * C.wtab[m * M + n] * J.recon[q]);
         }
@@ -661,17 +695,14 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         // the step's coefficient, recorded off the critical path (read only
         // after the loop)
         if (t == 0) {
-            H.car[it] = ar;
-            H.cai[it] = ai;
-            H.cidx[it] = IDX;
+            car[it] = ar;
+            cai[it] = ai;
+            cidx[it] = IDX;
             if (trace) trace[it] = IDX;
         }
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
     __syncthreads();  // the coefficient list is complete
-    const double* car = H.car;
-    const double* cai = H.cai;
-    const int32_t* cidx = H.cidx;
 
     // ---- synthesis at the block's lost pixels ------------------------------
     // gs threads per pixel, each summing every gs-th step; B*B pixels
@@ -712,8 +743,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S) {
-    const int4 d = const_load(J.desc + blk);
-    const int4 lb = const_load(J.lbox + blk);
+    const int4 d = uniform_load(J.desc + blk);
+    const int4 lb = uniform_load(J.lbox + blk);
     const ClassDev& Cj = a.cls[d.z];
     const int Bm = a.Bmin;
     // fine cells that may hold an interacting block
@@ -776,9 +807,12 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 4 : 1) k_fse_blo
         H.twc32[t] = a.tw32[t];
         H.tws32[t] = a.tw32[32 + t];
     }
-    if (t < 64) {
-        H.twc64[t] = a.tw64[t];
-        H.tws64[t] = a.tw64[64 + t];
+    double* tw64 = nullptr;
+    if constexpr (WIDE) {
+        Shared64& S = *reinterpret_cast<Shared64*>(smem_raw);
+        tw64 = S.tw64;
+        if (t < 128) tw64[t] = a.tw64[t];
+        buf = S.buf;
     }
     for (;;) {
         if (t == 0) {
@@ -800,15 +834,15 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 4 : 1) k_fse_blo
         __syncthreads();
         const int job = __builtin_amdgcn_readfirstlane(H.job), blk = __builtin_amdgcn_readfirstlane(H.blk);
         if (job < 0) break;
-        const JobDev J = const_load(a.jobs + job);
+        const JobDev J = uniform_load(a.jobs + job);
         if constexpr (WIDE) {
             // 64 x 64 windows on all waves; 32 x 32 windows on four of them
             if (a.cls[J.desc[blk].z].M == 64)
-                process_block<64, NW, NW, PREC>(a, J, blk, H, buf);
+                process_block<64, NW, NW, PREC>(a, J, blk, H, buf, tw64);
             else
-                process_block<32, 4, NW, PREC>(a, J, blk, H, buf);
+                process_block<32, 4, NW, PREC>(a, J, blk, H, buf, tw64);
         } else {
-            process_block<32, NW, NW, PREC>(a, J, blk, H, buf);
+            process_block<32, NW, NW, PREC>(a, J, blk, H, buf, tw64);
         }
         __syncthreads();
         if (t == 0) {

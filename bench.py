@@ -10,10 +10,11 @@ A step is one batched extrapolation of ``--batch`` requests on inputs already
 resident in HBM: host planning of every request's blocks and dependency
 order, upload of the plan, and one persistent dependency-driven kernel that
 runs the blocks of all requests.  ``value`` = processing blocks per second
-over the timed steps, which rotate over ``--streams`` streams (default four)
-so that the host planning of one batch and the launches of the batches
-before it overlap; the outputs are checked bitwise against steps run one at
-a time.  The roofline, the kernel time and the step latencies come from
+over the timed steps (default twelve), which rotate over ``--streams``
+streams (default four) so that the host planning of one batch and the
+launches of the batches before it overlap; the timed region starts and ends
+with an idle device, so it includes the filling and draining of that
+pipeline.  The outputs are checked bitwise against steps run one at a time.  The roofline, the kernel time and the step latencies come from
 those one-at-a-time steps (a launch alone on the device).  Also reported:
 one request alone, the paper's tile framework on one request, the tile-border
 and tiling comparisons, the 3840x2160 tiled batch, FP32 and BF16x3 against
@@ -160,7 +161,7 @@ def cpu_tile_framework(one_core_rate: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=16, help="1920x1080 requests per batched step")
     ap.add_argument("--no-autotune", action="store_true", help="use the automatic schedule instead of the autotuner")

@@ -13,7 +13,9 @@
  *
  * Conventions
  *  - Every call returns fse_status_t: FSE_OK (0) or a negative error code;
- *    fse_status_string() names it.  No C++ exception crosses the ABI.
+ *    fse_status_string() names it.  No C++ exception crosses the ABI: a host
+ *    allocation that fails inside a call returns FSE_ERR_OUT_OF_MEMORY, any
+ *    other failure of the host code FSE_ERR_INVALID_ARG.
  *  - Image, mask and output buffers are DEVICE pointers owned by the caller;
  *    they must stay valid until the work enqueued on `stream` (or the served
  *    request) has completed.  `stream` is a hipStream_t passed as void*
@@ -100,7 +102,7 @@ typedef struct {
  * each edge a multiple of the next; every class but the last takes aligned
  * squares that are entirely lost, the last class takes the aligned cells
  * that still hold a lost pixel.  Block edges are powers of two up to 16;
- * supported windows: M = 32.
+ * supported windows: M = 32 and M = 64.
  * rho in (0,1]: isotropic weight decay rho^distance; recon_weight in (0,1]:
  * extra factor for pixels reconstructed by earlier blocks; gamma in (0,2):
  * orthogonality-deficiency compensation.
@@ -220,6 +222,12 @@ fse_status_t fse_plan_create(int32_t n, const fse_mask_t* masks, const fse_param
  * the size of mask i.  Enqueued on `stream` as one graph launch; executions of
  * one plan are serialised (each waits until the previous one has finished). */
 fse_status_t fse_plan_execute(fse_plan_t* plan, const fse_image_t* images, fse_image_t* outs, void* stream);
+/* Statistics of the plan (blocks, lost pixels, jobs, planning time) and of
+ * its last execution: waits until that execution has finished and reports
+ * its device error word (non-zero: a dependency wait hit its time limit and
+ * the outputs are invalid) and its degenerate blocks.  kernel_ms is 0 (graph
+ * launches are not timed).  Before the first execution both words read 0. */
+fse_status_t fse_plan_stats(fse_plan_t* plan, fse_run_stats_t* st);
 fse_status_t fse_plan_destroy(fse_plan_t* plan);
 
 /* ---- serving: continuous batching of requests ------------------------- */
@@ -242,7 +250,11 @@ typedef struct {
 } fse_request_stats_t;
 
 fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** server);
-/* Queue a request.  The buffers are device pointers owned by the caller and
+/* Queue a request.  A request whose launch fails -- including a launch whose
+ * dependency wait hit its time limit (see fse_run_stats_t.device_error) --
+ * completes with that error (FSE_ERR_DEVICE) from fse_serve_wait and
+ * fse_serve_poll; its output is then invalid.
+ * The buffers are device pointers owned by the caller and
  * must stay valid until the request is done.  The server's streams are not
  * ordered after the caller's: image and mask must hold their final contents
  * when the request is submitted (synchronise the work that wrote them first).

@@ -47,20 +47,44 @@ def _load():
     global _lib
     if _lib is None:
         build()
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.POINTER
-        d, i, u8 = ctypes.c_double, ctypes.c_int, ctypes.c_uint8
-        lib.fse_oracle_block.restype = d
-        lib.fse_oracle_block.argtypes = [i, P(d), P(d), P(d), i, d, P(i), P(d), P(d), P(d), P(d), P(i)]
-        lib.fse_oracle_plan.restype = i
-        lib.fse_oracle_plan.argtypes = [P(u8), i, i, P(i), i, P(i), P(i), P(i), i, P(i)]
-        lib.fse_oracle_one_block.restype = d
-        lib.fse_oracle_one_block.argtypes = [P(d), P(u8), i, i, i, i, i, i, i, d, d, d, P(d), P(i)]
-        lib.fse_oracle_image.restype = i
-        lib.fse_oracle_image.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(i), P(d), i, P(i), P(d),
-                                         P(i), P(d), P(d)]
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+class variant:
+    """Context manager: the functions of this module run on another build of
+    the oracle's C code (a library at ``path``) until the block exits.  The
+    tests use it to show that the pins reject an oracle with a planted
+    mistake."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self._saved = _lib
+        _lib = _bind(ctypes.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self._saved
+        return False
+
+
+def _bind(lib):
+    P = ctypes.POINTER
+    d, i, u8 = ctypes.c_double, ctypes.c_int, ctypes.c_uint8
+    lib.fse_oracle_block.restype = d
+    lib.fse_oracle_block.argtypes = [i, P(d), P(d), P(d), i, d, P(i), P(d), P(d), P(d), P(d), P(i)]
+    lib.fse_oracle_plan.restype = i
+    lib.fse_oracle_plan.argtypes = [P(u8), i, i, P(i), i, P(i), P(i), P(i), i, P(i)]
+    lib.fse_oracle_one_block.restype = d
+    lib.fse_oracle_one_block.argtypes = [P(d), P(u8), i, i, i, i, i, i, i, d, d, d, P(d), P(i)]
+    lib.fse_oracle_image.restype = i
+    lib.fse_oracle_image.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(i), P(d), i, P(i), P(d),
+                                     P(i), P(d), P(d)]
+    return lib
 
 
 def _p(a, ctype):

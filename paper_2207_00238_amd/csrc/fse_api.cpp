@@ -87,6 +87,26 @@ Workspace* workspace_for(hipStream_t st, std::unique_lock<std::mutex>& lk) {
     return slot.get();
 }
 
+fse_status_t read_launch_error(hipStream_t st, int32_t* error) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    *error = 0;
+    std::lock_guard<std::mutex> rl(g_ws_mu);
+    auto it = g_ws.find({dev, st});
+    if (it == g_ws.end()) return FSE_OK;
+    Workspace& ws = *it->second;
+    std::lock_guard<std::mutex> wl(ws.mu);
+    if (!ws.misc.p) return FSE_OK;
+    // through the launch's own stream (idle by now): a copy on the null
+    // stream would also wait for the other streams of the device
+    int32_t w = 0;
+    hipError_t e = hipMemcpyAsync(&w, ws.misc.p, sizeof(w), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return from_hip(e);
+    *error = w;
+    return FSE_OK;
+}
+
 void release_workspace(int dev, hipStream_t st) {
     std::lock_guard<std::mutex> rl(g_ws_mu);
     auto it = g_ws.find({dev, st});
@@ -645,20 +665,22 @@ const char* fse_status_string(fse_status_t s) {
 }
 
 fse_status_t fse_params_default(fse_params_t* p) {
-    if (!p) return FSE_ERR_INVALID_ARG;
-    std::memset(p, 0, sizeof(*p));
-    p->n_classes = 1;
-    p->classes[0] = {4, 14, 100};
-    p->rho = 0.8;
-    p->gamma = 0.5;
-    p->recon_weight = 0.5;
-    p->precision = FSE_PREC_F64;
-    p->schedule = FSE_SCHED_PERSISTENT;
-    p->tiling = FSE_WHOLE;
-    p->n_tiles = 1;
-    p->overlap = 32;
-    p->align = 16;
-    return FSE_OK;
+    return abi_guard([&]() -> fse_status_t {
+        if (!p) return FSE_ERR_INVALID_ARG;
+        std::memset(p, 0, sizeof(*p));
+        p->n_classes = 1;
+        p->classes[0] = {4, 14, 100};
+        p->rho = 0.8;
+        p->gamma = 0.5;
+        p->recon_weight = 0.5;
+        p->precision = FSE_PREC_F64;
+        p->schedule = FSE_SCHED_PERSISTENT;
+        p->tiling = FSE_WHOLE;
+        p->n_tiles = 1;
+        p->overlap = 32;
+        p->align = 16;
+        return FSE_OK;
+    });
 }
 
 }  // extern "C"
@@ -700,125 +722,139 @@ static fse_status_t tiles_with_stripe(int32_t W, int32_t H, int32_t N, int32_t d
 extern "C" {
 
 fse_status_t fse_plan_tiles(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align, fse_tile_t* tiles) {
-    return tiles_with_stripe(W, H, N, d, align, false, tiles);
+    return abi_guard([&]() -> fse_status_t {
+        return tiles_with_stripe(W, H, N, d, align, false, tiles);
+    });
 }
 
 fse_status_t fse_plan_tiles_vertical(int32_t W, int32_t H, int32_t N, int32_t d, int32_t align,
                                      fse_tile_t* tiles) {
-    return tiles_with_stripe(W, H, N, d, align, true, tiles);
+    return abi_guard([&]() -> fse_status_t {
+        return tiles_with_stripe(W, H, N, d, align, true, tiles);
+    });
 }
 
 fse_status_t fse_extrapolate(const fse_image_t* image, const fse_mask_t* mask, const fse_params_t* p,
                              fse_image_t* out, void* stream) {
-    if (!image || !mask || !out) return FSE_ERR_INVALID_ARG;
-    return run_batch(1, image, mask, p, out, (hipStream_t)stream);
+    return abi_guard([&]() -> fse_status_t {
+        if (!image || !mask || !out) return FSE_ERR_INVALID_ARG;
+        return run_batch(1, image, mask, p, out, (hipStream_t)stream);
+    });
 }
 
 fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
                                    const fse_params_t* p, fse_image_t* outs, void* stream) {
-    return run_batch(n, images, masks, p, outs, (hipStream_t)stream);
+    return abi_guard([&]() -> fse_status_t {
+        return run_batch(n, images, masks, p, outs, (hipStream_t)stream);
+    });
 }
 
 fse_status_t fse_last_stats(fse_run_stats_t* st) {
-    if (!st) return FSE_ERR_INVALID_ARG;
-    // the last call's workspace, if it still exists (fse_release frees it)
-    Workspace* ws = nullptr;
-    std::unique_lock<std::mutex> lk;
-    if (g_last.gen) {
-        std::lock_guard<std::mutex> rl(g_ws_mu);
-        auto it = g_ws.find({g_last.dev, g_last.st});
-        if (it != g_ws.end() && it->second->gen == g_last.gen) {
-            ws = it->second.get();
-            lk = std::unique_lock<std::mutex>(ws->mu);
+    return abi_guard([&]() -> fse_status_t {
+        if (!st) return FSE_ERR_INVALID_ARG;
+        // the last call's workspace, if it still exists (fse_release frees it)
+        Workspace* ws = nullptr;
+        std::unique_lock<std::mutex> lk;
+        if (g_last.gen) {
+            std::lock_guard<std::mutex> rl(g_ws_mu);
+            auto it = g_ws.find({g_last.dev, g_last.st});
+            if (it != g_ws.end() && it->second->gen == g_last.gen) {
+                ws = it->second.get();
+                lk = std::unique_lock<std::mutex>(ws->mu);
+            }
         }
-    }
-    if (ws) {
-        hipError_t e = hipStreamSynchronize(ws->last_stream);
-        if (e != hipSuccess) return from_hip(e);
-        if (ws->timed) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ws->ev0, ws->ev1) == hipSuccess) g_last_stats.kernel_ms = ms;
+        if (ws) {
+            hipError_t e = hipStreamSynchronize(ws->last_stream);
+            if (e != hipSuccess) return from_hip(e);
+            if (ws->timed) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ws->ev0, ws->ev1) == hipSuccess) g_last_stats.kernel_ms = ms;
+            }
+            int32_t misc[4] = {0, 0, 0, 0};
+            if (ws->misc.p && hipMemcpy(misc, ws->misc.p, sizeof(misc), hipMemcpyDeviceToHost) == hipSuccess) {
+                g_last_stats.device_error = misc[0];
+                int64_t deg = 0;
+                std::memcpy(&deg, misc + 2, sizeof(deg));
+                g_last_stats.n_degenerate = deg;
+            }
         }
-        int32_t misc[4] = {0, 0, 0, 0};
-        if (ws->misc.p && hipMemcpy(misc, ws->misc.p, sizeof(misc), hipMemcpyDeviceToHost) == hipSuccess) {
-            g_last_stats.device_error = misc[0];
-            int64_t deg = 0;
-            std::memcpy(&deg, misc + 2, sizeof(deg));
-            g_last_stats.n_degenerate = deg;
-        }
-    }
-    *st = g_last_stats;
-    return FSE_OK;
+        *st = g_last_stats;
+        return FSE_OK;
+    });
 }
 
 fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
                           fse_image_t* outs, void* stream, fse_params_t* best) {
-    using namespace fse;
-    if (!best) return FSE_ERR_INVALID_ARG;
-    std::vector<ClassCfg> cls;
-    fse_status_t s = check_batch(n, images, masks, p, outs, cls);
-    if (s != FSE_OK) return s;
-    if (p->schedule != FSE_SCHED_PERSISTENT) return FSE_ERR_INVALID_ARG;
-    // workload signature: sizes, classes, precision, tiling
-    std::string key = std::to_string(p->precision) + "/" + std::to_string(p->tiling) + "/" +
-                      std::to_string(p->n_tiles) + "/" + std::to_string(p->overlap);
-    for (auto& c : cls) key += "/" + std::to_string(c.B) + "," + std::to_string(c.b) + "," + std::to_string(c.K);
-    for (int i = 0; i < n; ++i) key += "/" + std::to_string(images[i].width) + "x" + std::to_string(images[i].height);
-    static std::mutex cache_mu;
-    static std::map<std::string, std::pair<int, int>> cache;
-    *best = *p;
-    {
+    return abi_guard([&]() -> fse_status_t {
+        using namespace fse;
+        if (!best) return FSE_ERR_INVALID_ARG;
+        std::vector<ClassCfg> cls;
+        fse_status_t s = check_batch(n, images, masks, p, outs, cls);
+        if (s != FSE_OK) return s;
+        if (p->schedule != FSE_SCHED_PERSISTENT) return FSE_ERR_INVALID_ARG;
+        // workload signature: sizes, classes, precision, tiling
+        std::string key = std::to_string(p->precision) + "/" + std::to_string(p->tiling) + "/" +
+                          std::to_string(p->n_tiles) + "/" + std::to_string(p->overlap);
+        for (auto& c : cls) key += "/" + std::to_string(c.B) + "," + std::to_string(c.b) + "," + std::to_string(c.K);
+        for (int i = 0; i < n; ++i) key += "/" + std::to_string(images[i].width) + "x" + std::to_string(images[i].height);
+        static std::mutex cache_mu;
+        static std::map<std::string, std::pair<int, int>> cache;
+        *best = *p;
+        {
+            std::lock_guard<std::mutex> lk(cache_mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                best->block_waves = it->second.first;
+                best->workgroups = it->second.second;
+                return FSE_OK;
+            }
+        }
+        bool wide = false;
+        for (auto& c : cls) wide |= (c.M == 64);
+        // launches with 64 x 64 windows have a fixed workgroup shape (block_waves 0)
+        std::vector<int> waves = wide ? std::vector<int>{0} : std::vector<int>{2, 4};
+        double best_ms = 1e30;
+        int best_w = waves.front(), best_g = 0;
+        hipStream_t st = (hipStream_t)stream;
+        for (int w : waves) {
+            const int cap = persistent_grid(wide ? kWideWaves : w, p->precision, wide);
+            std::vector<int> grids{0};
+            for (int g : {128, 256, 384, 512, 768, 1024})
+                if (g < cap) grids.push_back(g);
+            grids.push_back(cap);
+            for (int g : grids) {
+                fse_params_t q = *p;
+                q.block_waves = w;
+                q.workgroups = g;
+                q.trace_sel = nullptr;
+                double ms = 0;
+                for (int rep = 0; rep < 2; ++rep) {
+                    if ((s = run_batch(n, images, masks, &q, outs, st)) != FSE_OK) return s;
+                    fse_run_stats_t rs{};
+                    if ((s = fse_last_stats(&rs)) != FSE_OK) return s;
+                    if (rs.device_error) return FSE_ERR_DEVICE;
+                    ms = rs.kernel_ms;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_w = w;
+                    best_g = g;
+                }
+            }
+        }
+        best->block_waves = best_w;
+        best->workgroups = best_g;
         std::lock_guard<std::mutex> lk(cache_mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) {
-            best->block_waves = it->second.first;
-            best->workgroups = it->second.second;
-            return FSE_OK;
-        }
-    }
-    bool wide = false;
-    for (auto& c : cls) wide |= (c.M == 64);
-    // launches with 64 x 64 windows have a fixed workgroup shape (block_waves 0)
-    std::vector<int> waves = wide ? std::vector<int>{0} : std::vector<int>{2, 4};
-    double best_ms = 1e30;
-    int best_w = waves.front(), best_g = 0;
-    hipStream_t st = (hipStream_t)stream;
-    for (int w : waves) {
-        const int cap = persistent_grid(wide ? kWideWaves : w, p->precision, wide);
-        std::vector<int> grids{0};
-        for (int g : {128, 256, 384, 512, 768, 1024})
-            if (g < cap) grids.push_back(g);
-        grids.push_back(cap);
-        for (int g : grids) {
-            fse_params_t q = *p;
-            q.block_waves = w;
-            q.workgroups = g;
-            q.trace_sel = nullptr;
-            double ms = 0;
-            for (int rep = 0; rep < 2; ++rep) {
-                if ((s = run_batch(n, images, masks, &q, outs, st)) != FSE_OK) return s;
-                fse_run_stats_t rs{};
-                if ((s = fse_last_stats(&rs)) != FSE_OK) return s;
-                if (rs.device_error) return FSE_ERR_DEVICE;
-                ms = rs.kernel_ms;
-            }
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_w = w;
-                best_g = g;
-            }
-        }
-    }
-    best->block_waves = best_w;
-    best->workgroups = best_g;
-    std::lock_guard<std::mutex> lk(cache_mu);
-    cache[key] = {best_w, best_g};
-    return FSE_OK;
+        cache[key] = {best_w, best_g};
+        return FSE_OK;
+    });
 }
 
 fse_status_t fse_release(void) {
-    release_all_workspaces();
-    return FSE_OK;
+    return abi_guard([&]() -> fse_status_t {
+        release_all_workspaces();
+        return FSE_OK;
+    });
 }
 
 }  // extern "C"

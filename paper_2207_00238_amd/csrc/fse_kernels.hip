@@ -143,7 +143,7 @@ struct SharedHead {
     // index and coefficient
     double2 sK[2][8];  // energy, index (low word)
     double2 sA[2][8];
-    int job, blk, wait_fail;
+    int job, blk;
     uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
 };
 
@@ -348,7 +348,7 @@ struct TileMap {
 };
 
 template <int NT>
-__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S);
+__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk);
 
 // NW waves compute the DFT and the K steps; the workgroup has NWG >= NW
 // waves, all of which stage the window, wait and synthesise (waves past NW
@@ -557,7 +557,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 
     // ---- wait for the earlier blocks this block depends on, then add their
     // reconstructed values to w*s
-    wait_predecessors<NT>(a, J, blk, H);
+    wait_predecessors<NT>(a, J, blk);
     // from here on the block is ready work: its waves issue ahead of the
     // pre-wait staging of other blocks on the same SIMDs
     __builtin_amdgcn_s_setprio(3);
@@ -705,9 +705,11 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     __syncthreads();  // the coefficient list is complete
 
     // ---- synthesis at the block's lost pixels ------------------------------
-    // gs threads per pixel, each summing every gs-th step; B*B pixels
+    // gs lanes of one wave per pixel, each summing every gs-th step; B*B
+    // pixels.  gs stays within a wave (at most 64): the lane sums are
+    // combined with shuffles, which do not cross waves.
     const int npx = B * B;
-    const int gs = npx >= NT ? 1 : NT / npx;
+    const int gs = npx >= NT ? 1 : min(64, NT / npx);
     const int sub = t % gs;
     for (int px = t / gs; px < npx; px += NT / gs) {
         const int py = px / B, pxx = px % B;
@@ -742,7 +744,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 // window, or whose window meets this block's lost pixels
 // ---------------------------------------------------------------------------
 template <int NT>
-__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk, SharedHead& S) {
+__device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk) {
     const int4 d = uniform_load(J.desc + blk);
     const int4 lb = uniform_load(J.lbox + blk);
     const ClassDev& Cj = a.cls[d.z];
@@ -776,7 +778,6 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk,
             while (ld_flag(&J.done[i]) == 0) {
                 __builtin_amdgcn_s_sleep(2);
                 if ((int64_t)(wall_clock64() - t0) > a.wait_limit) {
-                    S.wait_fail = 1;
                     atomicOr(a.error, 1);
                     break;
                 }
@@ -829,7 +830,6 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 4 : 1) k_fse_blo
                 H.job = -1;
                 H.blk = -1;
             }
-            H.wait_fail = 0;
         }
         __syncthreads();
         const int job = __builtin_amdgcn_readfirstlane(H.job), blk = __builtin_amdgcn_readfirstlane(H.blk);

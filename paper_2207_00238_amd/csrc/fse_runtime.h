@@ -6,6 +6,7 @@
 
 #include <deque>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "../../include/fse.h"
@@ -13,6 +14,20 @@
 #include "fse_plan.h"
 
 namespace fse {
+
+// The body of every C entry point runs inside this guard, so no C++
+// exception crosses the ABI: an allocation failure becomes OUT_OF_MEMORY,
+// any other exception (a size no container can hold) INVALID_ARG.
+template <class F>
+fse_status_t abi_guard(F&& body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return FSE_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        return FSE_ERR_INVALID_ARG;
+    }
+}
 
 // A grow-only device allocation.  Growing retires the old allocation to
 // `retired` (freed later, where waiting for the device is acceptable):
@@ -74,6 +89,10 @@ void fse_last_stats_nowait(fse_run_stats_t* st);
 // held by `lk` (taken while the registry is locked, so a concurrent release
 // cannot free it in between).
 Workspace* workspace_for(hipStream_t st, std::unique_lock<std::mutex>& lk);
+// The error word of the last launch on stream st (its workspace on the
+// current device): non-zero when a dependency wait hit its time limit.  The
+// launch must have completed.
+fse_status_t read_launch_error(hipStream_t st, int32_t* error);
 // free the workspace of one stream (before the stream is destroyed)
 void release_workspace(int dev, hipStream_t st);
 void release_all_workspaces();

@@ -7,7 +7,9 @@
 // on a free stream slot.  Launches on different slots run concurrently on the
 // device, so requests that arrive while earlier ones are on the GPU join the
 // next launch and overlap with them.  A launch's completion (an event on its
-// stream) releases its budget and marks its requests done.  Results do not
+// stream) releases its budget and marks its requests done -- or failed, when
+// the launch's error word reports a dependency wait that hit its time limit
+// or the event reports a device error.  Results do not
 // depend on what else is in a launch: every request keeps its own working
 // state and dependency order.
 #include <hip/hip_runtime.h>
@@ -100,98 +102,131 @@ static bool same_params(const fse_params_t& a, const fse_params_t& b) {
     return true;
 }
 
+// Marks the requests of a slot's launch finished with status st (FSE_OK:
+// done; otherwise failed) and frees the slot and its share of the budget.
+static void finish_slot(fse_server* S, Slot& sl, fse_status_t st) {
+    const double t = steady_ms();
+    for (auto& r : sl.reqs) {
+        r->t_done = t;
+        if (r->state == 1) {
+            r->state = st == FSE_OK ? 2 : 3;
+            r->status = st;
+        }
+    }
+    S->bytes_in_use -= sl.bytes;
+    sl.reqs.clear();
+    sl.bytes = 0;
+    sl.busy = false;
+    S->done_cv.notify_all();
+}
+
+// One pass of the scheduler with S->mu held by lk: retire finished launches,
+// then admit queued requests into a free slot.  Returns false once the
+// server is stopping and has nothing left to run.  An exception leaves the
+// server consistent: every allocation happens before the state changes.
+static bool schedule_once(fse_server* S, std::unique_lock<std::mutex>& lk) {
+    // retire finished launches: a launch whose dependency wait hit its time
+    // limit (the launch's error word) fails its requests, as does an error
+    // of the completion event itself
+    bool any_running = false;
+    for (auto& sl : S->slots) {
+        if (!sl.busy) continue;
+        const hipError_t q = hipEventQuery(sl.done_ev);
+        if (q == hipErrorNotReady) {
+            any_running = true;
+            continue;
+        }
+        fse_status_t st = from_hip(q);
+        if (st == FSE_OK) {
+            int32_t err = 0;
+            st = read_launch_error(sl.stream, &err);
+            if (st == FSE_OK && err) st = FSE_ERR_DEVICE;
+        }
+        finish_slot(S, sl, st);
+    }
+    if (S->stop && S->queue.empty() && !any_running) return false;
+    // admit: FIFO, by budget, one launch per free slot, same parameters per launch
+    int free_slot = -1;
+    for (size_t i = 0; i < S->slots.size(); ++i)
+        if (!S->slots[i].busy) {
+            free_slot = (int)i;
+            break;
+        }
+    if (free_slot >= 0 && !S->queue.empty()) {
+        std::vector<std::shared_ptr<Request>> take;
+        std::vector<fse_image_t> ims, outs;
+        std::vector<fse_mask_t> mks;
+        int64_t bytes = 0;
+        const fse_params_t p0 = S->queue.front()->params;
+        for (auto& r : S->queue) {
+            if (!same_params(r->params, p0)) continue;
+            if (S->bytes_in_use + bytes + r->bytes > S->cfg.hbm_budget_bytes) break;
+            bytes += r->bytes;
+            take.push_back(r);
+            ims.push_back(r->image);
+            outs.push_back(r->out);
+            mks.push_back(r->mask);
+        }
+        if (!take.empty()) {
+            // the picked requests leave the queue (in queue order; no allocation)
+            size_t k = 0;
+            S->queue.erase(std::remove_if(S->queue.begin(), S->queue.end(),
+                                          [&](const std::shared_ptr<Request>& r) {
+                                              if (k < take.size() && r == take[k]) {
+                                                  ++k;
+                                                  return true;
+                                              }
+                                              return false;
+                                          }),
+                           S->queue.end());
+            Slot& sl = S->slots[free_slot];
+            sl.busy = true;
+            sl.reqs.swap(take);
+            sl.bytes = bytes;
+            S->bytes_in_use += bytes;
+            const double t = steady_ms();
+            for (auto& r : sl.reqs) {
+                r->t_admit = t;
+                r->state = 1;
+            }
+            fse_params_t p = p0;
+            p.trace_sel = nullptr;
+            lk.unlock();
+            fse_status_t s = abi_guard(
+                [&] { return run_batch((int)ims.size(), ims.data(), mks.data(), &p, outs.data(), sl.stream); });
+            fse_run_stats_t st{};
+            fse_last_stats_nowait(&st);
+            if (s == FSE_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) s = FSE_ERR_DEVICE;
+            lk.lock();
+            const int64_t per = st.n_blocks / (int64_t)sl.reqs.size();
+            for (auto& r : sl.reqs) r->n_blocks = per;
+            if (s != FSE_OK) finish_slot(S, sl, s);
+            return true;  // try to fill another slot at once
+        }
+    }
+    S->cv.wait_for(lk, std::chrono::microseconds(any_running ? 100 : 2000));
+    return true;
+}
+
 static void scheduler(fse_server* S) {
-    int dev = S->cfg.device;
-    (void)hipSetDevice(dev);
+    (void)hipSetDevice(S->cfg.device);
     std::unique_lock<std::mutex> lk(S->mu);
-    while (true) {
-        // retire finished launches
-        bool any_running = false;
-        for (auto& sl : S->slots) {
-            if (!sl.busy) continue;
-            if (hipEventQuery(sl.done_ev) == hipSuccess) {
-                const double t = steady_ms();
-                for (auto& r : sl.reqs) {
-                    r->t_done = t;
-                    if (r->state == 1) r->state = 2;
-                }
-                S->bytes_in_use -= sl.bytes;
-                sl.reqs.clear();
-                sl.bytes = 0;
-                sl.busy = false;
+    for (;;) {
+        try {
+            if (!schedule_once(S, lk)) break;
+        } catch (...) {
+            // out of host memory while admitting: the request at the front of
+            // the queue fails, so that the next pass makes progress
+            if (!lk.owns_lock()) lk.lock();
+            if (!S->queue.empty()) {
+                std::shared_ptr<Request> r = S->queue.front();
+                S->queue.pop_front();
+                r->state = 3;
+                r->status = FSE_ERR_OUT_OF_MEMORY;
+                r->t_done = steady_ms();
                 S->done_cv.notify_all();
-            } else {
-                any_running = true;
             }
         }
-        if (S->stop && S->queue.empty() && !any_running) break;
-        // admit: FIFO, by budget, one launch per free slot, same parameters per launch
-        int free_slot = -1;
-        for (size_t i = 0; i < S->slots.size(); ++i)
-            if (!S->slots[i].busy) {
-                free_slot = (int)i;
-                break;
-            }
-        if (free_slot >= 0 && !S->queue.empty()) {
-            std::vector<std::shared_ptr<Request>> take;
-            int64_t bytes = 0;
-            const fse_params_t p0 = S->queue.front()->params;  // copy: the front may be taken below
-            for (auto it = S->queue.begin(); it != S->queue.end();) {
-                auto& r = *it;
-                if (!same_params(r->params, p0)) {
-                    ++it;
-                    continue;
-                }
-                if (S->bytes_in_use + bytes + r->bytes > S->cfg.hbm_budget_bytes) break;
-                bytes += r->bytes;
-                take.push_back(r);
-                it = S->queue.erase(it);
-            }
-            if (!take.empty()) {
-                Slot& sl = S->slots[free_slot];
-                sl.busy = true;
-                sl.reqs = take;
-                sl.bytes = bytes;
-                S->bytes_in_use += bytes;
-                const double t = steady_ms();
-                for (auto& r : take) {
-                    r->t_admit = t;
-                    r->state = 1;
-                }
-                std::vector<fse_image_t> ims, outs;
-                std::vector<fse_mask_t> mks;
-                for (auto& r : take) {
-                    ims.push_back(r->image);
-                    outs.push_back(r->out);
-                    mks.push_back(r->mask);
-                }
-                fse_params_t p = p0;
-                p.trace_sel = nullptr;
-                lk.unlock();
-                fse_status_t s = run_batch((int)take.size(), ims.data(), mks.data(), &p, outs.data(), sl.stream);
-                fse_run_stats_t st{};
-                fse_last_stats_nowait(&st);
-                if (s == FSE_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) s = FSE_ERR_DEVICE;
-                lk.lock();
-                const int64_t per = take.empty() ? 0 : st.n_blocks / (int64_t)take.size();
-                for (auto& r : take) r->n_blocks = per;
-                if (s != FSE_OK) {
-                    const double t2 = steady_ms();
-                    for (auto& r : take) {
-                        r->state = 3;
-                        r->status = s;
-                        r->t_done = t2;
-                    }
-                    S->bytes_in_use -= bytes;
-                    sl.busy = false;
-                    sl.reqs.clear();
-                    sl.bytes = 0;
-                    S->done_cv.notify_all();
-                }
-                continue;  // try to fill another slot at once
-            }
-        }
-        S->cv.wait_for(lk, std::chrono::microseconds(any_running ? 100 : 2000));
     }
 }
 
@@ -202,80 +237,90 @@ using namespace fse;
 extern "C" {
 
 fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** server) {
-    if (!cfg || !server || cfg->max_slots < 1 || cfg->max_slots > 16 || cfg->hbm_budget_bytes <= 0)
-        return FSE_ERR_INVALID_ARG;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return FSE_ERR_INVALID_ARG;
-    // the streams are created on the server's device; the caller's current
-    // device is restored on return
-    int prev_dev = 0;
-    (void)hipGetDevice(&prev_dev);
-    struct RestoreDevice {
-        int d;
-        ~RestoreDevice() { (void)hipSetDevice(d); }
-    } restore{prev_dev};
-    auto* S = new fse_server();
-    S->cfg = *cfg;
-    if (hipSetDevice(cfg->device) != hipSuccess) {
-        delete S;
-        return FSE_ERR_DEVICE;
-    }
-    S->slots.resize(cfg->max_slots);
-    // Slot streams with a CU mask (all CUs): such a stream is given a hardware
-    // queue of its own, while plain streams share the runtime's small queue
-    // pool with every other stream of the process -- two slots on one queue
-    // would run their launches one after the other.
-    int cus = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
-    std::vector<uint32_t> cu_mask((size_t)std::max(1, (cus + 31) / 32), 0xffffffffu);
-    for (auto& sl : S->slots) {
-        if (hipExtStreamCreateWithCUMask(&sl.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess) {
-            sl.stream = nullptr;
-            (void)hipGetLastError();
-            if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) sl.stream = nullptr;
-        }
-        if (!sl.stream || hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess) {
-            for (auto& s2 : S->slots) {
+    return abi_guard([&]() -> fse_status_t {
+        if (!cfg || !server || cfg->max_slots < 1 || cfg->max_slots > 16 || cfg->hbm_budget_bytes <= 0)
+            return FSE_ERR_INVALID_ARG;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return FSE_ERR_INVALID_ARG;
+        // the streams are created on the server's device; the caller's current
+        // device is restored on return
+        int prev_dev = 0;
+        (void)hipGetDevice(&prev_dev);
+        struct RestoreDevice {
+            int d;
+            ~RestoreDevice() { (void)hipSetDevice(d); }
+        } restore{prev_dev};
+        // streams and events are destroyed, and the server freed, on every
+        // early return (and on an exception)
+        auto cleanup = [](fse_server* q) {
+            for (auto& s2 : q->slots) {
                 if (s2.stream) (void)hipStreamDestroy(s2.stream);
                 if (s2.done_ev) (void)hipEventDestroy(s2.done_ev);
             }
-            delete S;
-            return FSE_ERR_DEVICE;
+            delete q;
+        };
+        std::unique_ptr<fse_server, decltype(cleanup)> holder(new fse_server(), cleanup);
+        fse_server* S = holder.get();
+        S->cfg = *cfg;
+        if (hipSetDevice(cfg->device) != hipSuccess) return FSE_ERR_DEVICE;
+        S->slots.resize(cfg->max_slots);
+        // Slot streams with a CU mask (all CUs): such a stream is given a hardware
+        // queue of its own, while plain streams share the runtime's small queue
+        // pool with every other stream of the process -- two slots on one queue
+        // would run their launches one after the other.
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device);
+        std::vector<uint32_t> cu_mask((size_t)std::max(1, (cus + 31) / 32), 0xffffffffu);
+        for (auto& sl : S->slots) {
+            if (hipExtStreamCreateWithCUMask(&sl.stream, (uint32_t)cu_mask.size(), cu_mask.data()) != hipSuccess) {
+                sl.stream = nullptr;
+                (void)hipGetLastError();
+                if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) sl.stream = nullptr;
+            }
+            if (!sl.stream || hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess)
+                return FSE_ERR_DEVICE;
         }
-    }
-    S->worker = std::thread(scheduler, S);
-    *server = S;
-    return FSE_OK;
+        S->worker = std::thread(scheduler, S);
+        *server = holder.release();
+        return FSE_OK;
+    });
 }
 
 fse_status_t fse_serve_submit(fse_server_t* S, const fse_image_t* image, const fse_mask_t* mask,
                               const fse_params_t* p, fse_image_t* out, uint64_t* ticket) {
-    if (!S || !image || !mask || !p || !out || !ticket) return FSE_ERR_INVALID_ARG;
-    std::vector<ClassCfg> cls;
-    fse_status_t s = check_params(p, cls);
-    if (s != FSE_OK) return s;
-    if (!image->data || !out->data || !mask->data || image->width < 1 || image->height < 1 ||
-        mask->width != image->width || mask->height != image->height || out->width != image->width ||
-        out->height != image->height || image->pitch < image->width || out->pitch < out->width ||
-        mask->pitch < mask->width || out->data == image->data)
-        return FSE_ERR_INVALID_ARG;
-    auto r = std::make_shared<Request>();
-    r->image = *image;
-    r->mask = *mask;
-    r->out = *out;
-    r->params = *p;
-    r->params.trace_sel = nullptr;
-    r->bytes = request_bytes(*image, *p);
-    if (r->bytes > S->cfg.hbm_budget_bytes) return FSE_ERR_BUDGET;
-    r->t_submit = steady_ms();
-    std::lock_guard<std::mutex> lk(S->mu);
-    if (S->stop) return FSE_ERR_BUSY;
-    r->ticket = S->next_ticket++;
-    S->queue.push_back(r);
-    S->all[r->ticket] = r;
-    *ticket = r->ticket;
-    S->cv.notify_one();
-    return FSE_OK;
+    return abi_guard([&]() -> fse_status_t {
+        if (!S || !image || !mask || !p || !out || !ticket) return FSE_ERR_INVALID_ARG;
+        std::vector<ClassCfg> cls;
+        fse_status_t s = check_params(p, cls);
+        if (s != FSE_OK) return s;
+        if (!image->data || !out->data || !mask->data || image->width < 1 || image->height < 1 ||
+            mask->width != image->width || mask->height != image->height || out->width != image->width ||
+            out->height != image->height || image->pitch < image->width || out->pitch < out->width ||
+            mask->pitch < mask->width || out->data == image->data)
+            return FSE_ERR_INVALID_ARG;
+        auto r = std::make_shared<Request>();
+        r->image = *image;
+        r->mask = *mask;
+        r->out = *out;
+        r->params = *p;
+        r->params.trace_sel = nullptr;
+        r->bytes = request_bytes(*image, *p);
+        if (r->bytes > S->cfg.hbm_budget_bytes) return FSE_ERR_BUDGET;
+        r->t_submit = steady_ms();
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return FSE_ERR_BUSY;
+        r->ticket = S->next_ticket++;
+        S->all[r->ticket] = r;
+        try {
+            S->queue.push_back(r);
+        } catch (...) {
+            S->all.erase(r->ticket);
+            throw;
+        }
+        *ticket = r->ticket;
+        S->cv.notify_one();
+        return FSE_OK;
+    });
 }
 
 static void fill_stats(const Request& r, fse_request_stats_t* st) {
@@ -287,69 +332,77 @@ static void fill_stats(const Request& r, fse_request_stats_t* st) {
 }
 
 fse_status_t fse_serve_poll(fse_server_t* S, uint64_t ticket, int32_t* done, fse_request_stats_t* st) {
-    if (!S || !done) return FSE_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(S->mu);
-    auto it = S->all.find(ticket);
-    if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
-    const Request& r = *it->second;
-    *done = r.state >= 2;
-    fill_stats(r, st);
-    return r.state == 3 ? r.status : FSE_OK;
+    return abi_guard([&]() -> fse_status_t {
+        if (!S || !done) return FSE_ERR_INVALID_ARG;
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->all.find(ticket);
+        if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
+        const Request& r = *it->second;
+        *done = r.state >= 2;
+        fill_stats(r, st);
+        return r.state == 3 ? r.status : FSE_OK;
+    });
 }
 
 fse_status_t fse_serve_wait(fse_server_t* S, uint64_t ticket, int64_t timeout_us, fse_request_stats_t* st) {
-    if (!S) return FSE_ERR_INVALID_ARG;
-    std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->all.find(ticket);
-    if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
-    auto r = it->second;
-    auto pred = [&] { return r->state >= 2; };
-    if (timeout_us < 0) {
-        S->done_cv.wait(lk, pred);
-    } else if (!S->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), pred)) {
-        return FSE_ERR_TIMEOUT;
-    }
-    fill_stats(*r, st);
-    const fse_status_t s = r->state == 3 ? r->status : FSE_OK;
-    S->all.erase(ticket);
-    return s;
+    return abi_guard([&]() -> fse_status_t {
+        if (!S) return FSE_ERR_INVALID_ARG;
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->all.find(ticket);
+        if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
+        auto r = it->second;
+        auto pred = [&] { return r->state >= 2; };
+        if (timeout_us < 0) {
+            S->done_cv.wait(lk, pred);
+        } else if (!S->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us), pred)) {
+            return FSE_ERR_TIMEOUT;
+        }
+        fill_stats(*r, st);
+        const fse_status_t s = r->state == 3 ? r->status : FSE_OK;
+        S->all.erase(ticket);
+        return s;
+    });
 }
 
 fse_status_t fse_serve_cancel(fse_server_t* S, uint64_t ticket) {
-    if (!S) return FSE_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lk(S->mu);
-    auto it = S->all.find(ticket);
-    if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
-    const std::shared_ptr<Request> r = it->second;
-    if (r->state != 0) return FSE_ERR_BUSY;  // admitted into a launch (or finished): it runs to the end
-    S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
-    r->state = 3;
-    r->status = FSE_ERR_CANCELLED;
-    r->t_done = steady_ms();
-    S->done_cv.notify_all();
-    return FSE_OK;
+    return abi_guard([&]() -> fse_status_t {
+        if (!S) return FSE_ERR_INVALID_ARG;
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->all.find(ticket);
+        if (it == S->all.end()) return FSE_ERR_NOT_FOUND;
+        const std::shared_ptr<Request> r = it->second;
+        if (r->state != 0) return FSE_ERR_BUSY;  // admitted into a launch (or finished): it runs to the end
+        S->queue.erase(std::remove(S->queue.begin(), S->queue.end(), r), S->queue.end());
+        r->state = 3;
+        r->status = FSE_ERR_CANCELLED;
+        r->t_done = steady_ms();
+        S->done_cv.notify_all();
+        return FSE_OK;
+    });
 }
 
 fse_status_t fse_serve_destroy(fse_server_t* S) {
-    if (!S) return FSE_ERR_INVALID_ARG;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stop = true;
-        S->cv.notify_all();
-    }
-    if (S->worker.joinable()) S->worker.join();
-    int prev_dev = 0;
-    (void)hipGetDevice(&prev_dev);
-    (void)hipSetDevice(S->cfg.device);
-    for (auto& sl : S->slots) {
-        (void)hipStreamSynchronize(sl.stream);
-        release_workspace(S->cfg.device, sl.stream);  // the slot's device tables and staging
-        (void)hipStreamDestroy(sl.stream);
-        (void)hipEventDestroy(sl.done_ev);
-    }
-    (void)hipSetDevice(prev_dev);
-    delete S;
-    return FSE_OK;
+    return abi_guard([&]() -> fse_status_t {
+        if (!S) return FSE_ERR_INVALID_ARG;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+            S->cv.notify_all();
+        }
+        if (S->worker.joinable()) S->worker.join();
+        int prev_dev = 0;
+        (void)hipGetDevice(&prev_dev);
+        (void)hipSetDevice(S->cfg.device);
+        for (auto& sl : S->slots) {
+            (void)hipStreamSynchronize(sl.stream);
+            release_workspace(S->cfg.device, sl.stream);  // the slot's device tables and staging
+            (void)hipStreamDestroy(sl.stream);
+            (void)hipEventDestroy(sl.done_ev);
+        }
+        (void)hipSetDevice(prev_dev);
+        delete S;
+        return FSE_OK;
+    });
 }
 
 }  // extern "C"

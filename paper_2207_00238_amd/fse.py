@@ -32,7 +32,7 @@ FSE_MAX_CLASSES = 3
 EXPORTED = [
     "fse_status_string", "fse_params_default", "fse_plan_tiles", "fse_extrapolate", "fse_extrapolate_batch",
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
-    "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy",
+    "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy", "fse_plan_stats",
     "fse_autotune", "fse_plan_tiles_vertical", "fse_serve_cancel",
 ]
 
@@ -135,6 +135,8 @@ def lib():
         L.fse_plan_execute.argtypes = [ctypes.c_void_p, P(fse_image_t), P(fse_image_t), ctypes.c_void_p]
         L.fse_plan_destroy.restype = st
         L.fse_plan_destroy.argtypes = [ctypes.c_void_p]
+        L.fse_plan_stats.restype = st
+        L.fse_plan_stats.argtypes = [ctypes.c_void_p, P(fse_run_stats_t)]
         _lib = L
     return _lib
 
@@ -308,6 +310,14 @@ def fse_plan_execute(plan, images, outs, stream=None) -> None:
     ims = (fse_image_t * n)(*[_image(t) for t in images])
     ots = (fse_image_t * n)(*[_image(t) for t in outs])
     check(lib().fse_plan_execute(plan, ims, ots, _stream(stream)), "fse_plan_execute")
+
+
+def fse_plan_stats(plan) -> dict:
+    """Plan statistics and the device error word of its last execution
+    (waits for that execution)."""
+    s = fse_run_stats_t()
+    check(lib().fse_plan_stats(plan, ctypes.byref(s)), "fse_plan_stats")
+    return {k: getattr(s, k) for k, _ in fse_run_stats_t._fields_}
 
 
 def fse_plan_destroy(plan) -> None:

@@ -19,14 +19,18 @@ def mirror(q, M):
 
 
 def compare_traces(sel_gpu, tr, M, K, tol=1e-5):
-    """sel_gpu: (n_blocks, >=K) int array; tr: oracle trace dict.
+    """sel_gpu: (n_blocks, >=K) int array; tr: oracle trace dict; M and K the
+    window size and step count, one for all blocks or one per block.
     Returns dict(flips, divergences_ok, divergences_bad, bad_examples)."""
     flips = ok = bad = 0
     examples = []
     n = tr["sel"].shape[0]
+    Ms = np.broadcast_to(np.asarray(M), (n,))
+    Ks = np.broadcast_to(np.asarray(K), (n,))
     for b in range(n):
         o = False
-        for t in range(K):
+        M = int(Ms[b])
+        for t in range(int(Ks[b])):
             p = int(tr["sel"][b, t])
             if p < 0:
                 break

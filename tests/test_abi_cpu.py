@@ -102,3 +102,28 @@ def test_serve_create_rejects_bad_config():
                 fse.fse_serve_config_t(1 << 20, 99, 0, 0)]:
         assert L.fse_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == fse.FSE_ERR_INVALID_ARG
     assert L.fse_serve_destroy(None) == fse.FSE_ERR_INVALID_ARG
+
+
+_OOM_CHILD = r"""
+import resource, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2207_00238_amd import fse
+L = fse.lib()
+N = 50_000_000
+tiles = (fse.fse_tile_t * N)()  # caller-owned, mapped lazily, never written on this path
+vm = next(int(l.split()[1]) * 1024 for l in open("/proc/self/status") if l.startswith("VmSize:"))
+# address space for a few hundred MB more: the planner's 800 MB tile list cannot be allocated
+resource.setrlimit(resource.RLIMIT_AS, (vm + (256 << 20), resource.RLIM_INFINITY))
+print(L.fse_plan_tiles(40000, 40000, N, 32, 1, tiles), flush=True)
+"""
+
+
+def test_host_allocation_failure_returns_status():
+    # a host allocation that fails inside an entry point comes back as
+    # FSE_ERR_OUT_OF_MEMORY instead of terminating the caller (no C++
+    # exception crosses the ABI); run in a child with a capped address space
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", _OOM_CHILD, ROOT], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert int(r.stdout.strip().splitlines()[-1]) == fse.FSE_ERR_OUT_OF_MEMORY

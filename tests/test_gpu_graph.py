@@ -69,3 +69,31 @@ def test_autotune_returns_equivalent_schedule():
     # cached: the second call returns the same schedule
     best2 = fse.fse_autotune([img], [msk], p, [out_a])
     assert (best2.block_waves, best2.workgroups) == (best.block_waves, best.workgroups)
+
+
+def test_plan_stats_reports_the_error_word(monkeypatch):
+    # fse_plan_stats waits for the last execution and reports its error word:
+    # set when the plan was prepared with a (host-forced, zero) wait limit,
+    # clear for a plan prepared with the normal limit
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    W, H = 256, 192
+    img = torch.from_numpy(synth.synth_image(W, H, seed=91, period_max=128.0)).to(dev)
+    msk = torch.from_numpy(synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=92)).to(dev)
+    p = fse.fse_params_default(classes=((4, 14, 30),), workgroups=256)
+    out = torch.empty_like(img)
+    for limit, expect_error in (("0", True), (None, False)):
+        if limit is None:
+            monkeypatch.delenv("FSE_WAIT_LIMIT_US", raising=False)
+        else:
+            monkeypatch.setenv("FSE_WAIT_LIMIT_US", limit)
+        plan = fse.fse_plan_create([msk], p)
+        try:
+            assert fse.fse_plan_stats(plan)["device_error"] == 0  # before any execution
+            fse.fse_plan_execute(plan, [img], [out])
+            st = fse.fse_plan_stats(plan)
+            assert st["n_blocks"] > 0
+            assert (st["device_error"] != 0) == expect_error
+        finally:
+            fse.fse_plan_destroy(plan)

@@ -46,8 +46,9 @@ def _check(img, mask, classes, schedule=0, gt=None, **kw):
     m = mask.astype(bool)
     assert np.array_equal(got[~m], np.asarray(img, np.float32)[~m]), "known pixels changed"
     rep = pixel_report(got, ref, img if gt is None else gt, mask)
-    M = classes[-1][0] + 2 * classes[-1][1]
-    cmp = compare_traces(sel, tr, M, classes[-1][2])
+    cb = O.plan(mask, classes)[2]
+    M = np.array([classes[c][0] + 2 * classes[c][1] for c in cb], dtype=np.int64)
+    cmp = compare_traces(sel, tr, M, np.array([classes[c][2] for c in cb], dtype=np.int64))
     print(rep, cmp, st)
     assert cmp["divergences_bad"] == 0, cmp
     assert rep["max_abs"] <= TIGHT, rep
@@ -237,6 +238,25 @@ def test_single_class_64_window():
     mask = synth.mask_blocks(128, 96, 8, 0.15, seed=94)
     cls = ((8, 28, 60),)
     _check(img, mask, cls)
+
+
+# Two-pixel blocks: four lost pixels per block, so the synthesis spreads one
+# pixel over many lanes -- within one wave also in eight-wave workgroups
+# (64 x 64 windows present) and with one, two or four waves per block.
+@pytest.mark.parametrize("cls,waves", [
+    (((2, 31, 40),), 0),                # 64 x 64 window, eight waves
+    (((8, 28, 30), (2, 15, 40)), 0),    # 2 x 2 blocks with 32 x 32 windows in an eight-wave launch
+    (((2, 15, 40),), 1),
+    (((2, 15, 40),), 2),
+    (((2, 15, 40),), 4),
+])
+def test_two_pixel_blocks(cls, waves):
+    W, H = 120, 88
+    img = synth.synth_image(W, H, seed=95, period_max=64.0)
+    mask = synth.mask_blocks_and_pixels(W, H, 2, 0.2, 0.01, seed=96)
+    if cls[0][0] == 8:
+        mask |= synth.mask_blocks(W, H, 8, 0.1, seed=97)
+    _check(img, mask, cls, block_waves=waves)
 
 
 @pytest.mark.parametrize("d", [0, 1, 2, 4, 6, 8])

@@ -173,3 +173,35 @@ def test_mixed_parameters_in_one_server():
         fse.fse_serve_destroy(srv)
     for k, (_, _, _, alone, o) in enumerate(cases):
         assert torch.equal(alone, o), f"request {k}: served differs from alone"
+
+
+def test_wait_limit_error_fails_the_served_request(monkeypatch):
+    # a launch whose dependency wait hits its (host-forced, zero) time limit
+    # reports its error word; the server fails that request with
+    # FSE_ERR_DEVICE instead of serving the invalid result, and a request
+    # served afterwards with the normal limit is clean
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    img, mask = _inputs(256, 192, 91, "pixels")
+    ti = torch.from_numpy(img).to(dev)
+    tm = torch.from_numpy(mask).to(dev)
+    p = fse.fse_params_default(classes=((4, 14, 30),), workgroups=256)
+    o = torch.full_like(ti, -1.0)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("FSE_WAIT_LIMIT_US", "0")
+    srv = fse.fse_serve_create(hbm_budget_bytes=1 << 30, max_slots=2)
+    try:
+        t = fse.fse_serve_submit(srv, ti, tm, p, o)
+        with pytest.raises(fse.FseError) as ei:
+            fse.fse_serve_wait(srv, t, 60_000_000)
+        assert ei.value.status == fse.FSE_ERR_DEVICE
+        monkeypatch.delenv("FSE_WAIT_LIMIT_US")
+        o2 = torch.full_like(ti, -1.0)
+        t2 = fse.fse_serve_submit(srv, ti, tm, p, o2)
+        fse.fse_serve_wait(srv, t2, 60_000_000)
+    finally:
+        fse.fse_serve_destroy(srv)
+    ref = O.image(img, mask, ((4, 14, 30),))
+    m = mask.astype(bool)
+    assert np.abs(o2.cpu().numpy() - ref)[m].max() <= TIGHT

@@ -9,14 +9,24 @@ the paper, independent of the oracle's own code.
 * Single-basis recovery: a complex exponential inside the support is
   recovered exactly in one step with gamma = 1; real checkerboard/stripe and
   constant images are recovered exactly at image level.
+* Synthesis and weights: a real oblique sinusoid (3, 5 cycles per window)
+  is recovered at the lost pixels; the oracle's single blocks (windows
+  mixing known, lost, reconstructed and off-image pixels) and whole images
+  equal an independent NumPy brute force (tests/npfse.py).  Mistakes planted
+  in a copy of the oracle's C code (the synthesis exponent's sign, the
+  synthesis offset, the reconstructed-pixel factor, the decay centre) are
+  each rejected by one of these pins.
 * Lost input values are never read (NaN poisoning).
 * Raster order vs any dependency-respecting order: identical results.
 """
 import math
+import os
+import subprocess
 
 import numpy as np
 import pytest
 
+import npfse
 from oracle import oracle as O
 from paper_2207_00238_amd import synth
 
@@ -238,3 +248,114 @@ def test_tiles_differ_slightly_for_dense_losses_oracle():
     from parity import psnr
     d = abs(psnr(whole, img, m) - psnr(tiled, img, m))
     assert d < 0.5
+
+
+# ---------------------------------------------------------------------------
+# Synthesis and weights, pinned against things other than the oracle itself:
+# a real oblique sinusoid (not a DC or Nyquist pattern, so the sign of the
+# synthesis exponent and the window offset matter) and the NumPy brute-force
+# checker of tests/npfse.py (weights from R7, spectra by numpy.fft.fft2, the
+# residual kept in the pixel domain, synthesis by direct exponentials).
+# ---------------------------------------------------------------------------
+ORACLE_C = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "fse_oracle.c")
+
+
+def _oblique_error(gamma, K):
+    # 120 + 40 sin(2 pi (3y + 5x) / 32 + 0.7) lies in the span of three basis
+    # functions of every 32 x 32 window (DC, (3, 5) and (-3, -5)), so the fit
+    # converges to it at the lost pixels
+    H, W = 96, 128
+    y = np.arange(H)[:, None]
+    x = np.arange(W)[None, :]
+    img = 120.0 + 40.0 * np.sin(2 * np.pi * (3 * y + 5 * x) / 32 + 0.7)
+    mask = synth.mask_blocks(W, H, 4, 0.3, seed=5)
+    out = O.image(img, mask, ((4, 14, K),), gamma=gamma)
+    return float(np.abs(out - img)[mask.astype(bool)].max())
+
+
+def _mixed_state(seed=5):
+    # values with every pixel status: known, lost (values must not matter),
+    # reconstructed; windows below also reach off the image
+    rng = np.random.default_rng(seed)
+    H, W = 70, 90
+    val = synth.synth_image(W, H, seed=3).astype(np.float64)
+    status = np.zeros((H, W), np.uint8)
+    status[rng.random((H, W)) < 0.15] = npfse.LOST
+    status[rng.random((H, W)) < 0.15] = npfse.RECON
+    val[status == npfse.LOST] = np.nan
+    return val, status
+
+
+# (y0, x0, B, b, K): interior, corners (off-image pixels), both window sizes
+BLOCKS = [(20, 30, 4, 14, 100), (0, 0, 4, 14, 60), (64, 84, 4, 14, 80), (8, 40, 8, 28, 120),
+          (40, 8, 16, 24, 150), (30, 50, 2, 15, 90)]
+
+
+def _checker_error():
+    val, status = _mixed_state()
+    worst = 0.0
+    for (y0, x0, B, b, K) in BLOCKS:
+        a, _, w0a = O.one_block(val, status, y0, x0, B, b, K)
+        c, _, w0c = npfse.one_block(val, status, y0, x0, B, b, K)
+        worst = max(worst, float(np.abs(a - c).max() / np.abs(c).max()), abs(w0a - w0c) / w0c)
+    return worst
+
+
+@pytest.mark.parametrize("gamma,K,tol", [(1.0, 100, 1e-9), (0.5, 100, 1e-6)])
+def test_oblique_sinusoid_recovered_at_lost_pixels(gamma, K, tol):
+    assert _oblique_error(gamma, K) < tol
+
+
+def test_one_block_matches_numpy_bruteforce():
+    assert _checker_error() < 1e-9
+
+
+def test_image_matches_numpy_bruteforce():
+    # the raster process itself (block plan, owners, lost -> reconstructed)
+    img = synth.synth_image(72, 56, seed=13)
+    mask = synth.mask_mixed(72, 56, seed=14, frac8=0.1, frac16=0.1, row_fraction=0.05)
+    cls = ((16, 24, 20), (8, 28, 20), (4, 14, 20))
+    blocks, owner = npfse.plan(mask, cls)
+    y, x, c, owner_o = O.plan(mask, cls)
+    assert [tuple(v) for v in blocks] == list(zip(y.tolist(), x.tolist(), c.tolist()))
+    assert np.array_equal(owner, owner_o)
+    a = npfse.image(img, mask, cls)
+    b = O.image(img, mask, cls)
+    assert np.abs(a - b).max() < 1e-9 * np.abs(a).max()
+
+
+# Mistakes planted in a copy of the oracle's C code, each with the pin that
+# must reject it.  The copy is compiled on the CPU and loaded in place of the
+# oracle for the duration of the check.
+PLANTED = [
+    ("flipped sign of the synthesis exponent", "oblique",
+     "        double s = sin(TWO_PI * (double)p / (double)M);\n",
+     "        double s = -sin(TWO_PI * (double)p / (double)M);\n"),
+    ("synthesis one row off the block", "oblique",
+     "if (W0 > 0.0) synth_at(M, K, sel, ar, ai, m, n, &gr, &gi);",
+     "if (W0 > 0.0) synth_at(M, K, sel, ar, ai, m + 1, n, &gr, &gi);"),
+    ("delta on known instead of reconstructed pixels", "checker",
+     "            if (st == ST_KNOWN) wt = pow(rho, dist);\n"
+     "            else if (st == ST_RECON) wt = delta * pow(rho, dist);\n",
+     "            if (st == ST_KNOWN) wt = delta * pow(rho, dist);\n"
+     "            else if (st == ST_RECON) wt = pow(rho, dist);\n"),
+    ("decay centred at M/2", "checker",
+     "    double ctr = 0.5 * (double)(M - 1);\n",
+     "    double ctr = 0.5 * (double)M;\n"),
+]
+
+
+@pytest.mark.parametrize("name,pin,old,new", PLANTED, ids=[p[0] for p in PLANTED])
+def test_pins_reject_a_planted_mistake(name, pin, old, new, tmp_path):
+    src = open(ORACLE_C).read()
+    assert src.count(old) == 1, f"planted mistake '{name}' no longer applies"
+    (tmp_path / "variant.c").write_text(src.replace(old, new))
+    so = str(tmp_path / "libvariant.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", so, str(tmp_path / "variant.c"), "-lm"])
+    with O.variant(so):
+        if pin == "oblique":
+            assert _oblique_error(0.5, 100) > 1.0, name
+        else:
+            assert _checker_error() > 1e-6, name
+    # the real oracle passes the same pin
+    assert _oblique_error(0.5, 100) < 1e-6 and _checker_error() < 1e-9

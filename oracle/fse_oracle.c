@@ -354,6 +354,125 @@ double fse_oracle_one_block(const double* val, const unsigned char* status, int 
 }
 
 /*
+ * Optimised processing order (Sec. II: the order follows the shape and the
+ * distribution of the lost pixels, so that large lost areas close from their
+ * margins towards their centre).  The rule itself is in work the paper cites
+ * and does not print; the reading implemented here (R17):
+ *
+ *   Each step processes, among the blocks not yet processed, the block whose
+ *   support window currently offers the largest share of usable weight: the
+ *   sum of its window weights under the current pixel statuses (R7: rho^dist
+ *   for known pixels, delta rho^dist for reconstructed ones, 0 for lost or
+ *   off-image pixels), divided by that sum for a window of its class whose
+ *   pixels are all known.  Equal shares go to the block that comes first in
+ *   raster order.
+ *
+ * The weights enter as integers, q = round(2^30 rho^dist) and
+ * qr = round(2^30 delta rho^dist), so every sum is exact and every tie is a
+ * true tie; shares are compared by cross-multiplication in 128-bit integers.
+ * The order depends on the mask alone.
+ *
+ * Plain implementation: after each step the share of every remaining block
+ * whose window meets the processed block is summed again over its whole
+ * window from the status map, and the next block is found by a scan over all
+ * blocks.  order[k] receives the raster index of the k-th block processed
+ * (order has room for every block).  Returns the number of blocks, or -1.
+ */
+typedef unsigned __int128 u128;
+
+static long long q_weight(double rho, double delta, int M, int m, int n, int recon) {
+    double dm = m - (M - 1) / 2.0, dn = n - (M - 1) / 2.0; /* from the window centre */
+    double wt = pow(rho, sqrt(dm * dm + dn * dn));
+    if (recon) wt = delta * wt;
+    return llround(ldexp(wt, 30));
+}
+
+static long long window_share_sum(const unsigned char* status, int W, int H, int wy, int wx, int M,
+                                  const long long* qk, const long long* qr) {
+    long long sum = 0;
+    for (int m = 0; m < M; ++m)
+        for (int n = 0; n < M; ++n) {
+            int y = wy + m, x = wx + n;
+            if (y < 0 || y >= H || x < 0 || x >= W) continue;
+            unsigned char st = status[(size_t)y * W + x];
+            if (st == ST_KNOWN) sum += qk[m * M + n];
+            else if (st == ST_RECON) sum += qr[m * M + n];
+        }
+    return sum;
+}
+
+int fse_oracle_priority_order(const unsigned char* mask, int W, int H, const int* classes, int n_classes,
+                              double rho, double delta, int* order) {
+    if (W <= 0 || H <= 0 || n_classes <= 0 || n_classes > 8 || !order) return -1;
+    int nb = fse_oracle_plan(mask, W, H, classes, n_classes, NULL, NULL, NULL, 0, NULL);
+    int nmax = nb < 0 ? -nb : nb;
+    int* by = (int*)malloc(sizeof(int) * (nmax + 1));
+    int* bx = (int*)malloc(sizeof(int) * (nmax + 1));
+    int* bc = (int*)malloc(sizeof(int) * (nmax + 1));
+    int* owner = (int*)malloc(sizeof(int) * (size_t)W * H);
+    nb = fse_oracle_plan(mask, W, H, classes, n_classes, by, bx, bc, nmax, owner);
+
+    long long* qk[8];
+    long long* qr[8];
+    long long full[8];
+    for (int c = 0; c < n_classes; ++c) {
+        int M = classes[3 * c] + 2 * classes[3 * c + 1];
+        qk[c] = (long long*)malloc(sizeof(long long) * M * M);
+        qr[c] = (long long*)malloc(sizeof(long long) * M * M);
+        full[c] = 0;
+        for (int m = 0; m < M; ++m)
+            for (int n = 0; n < M; ++n) {
+                qk[c][m * M + n] = q_weight(rho, delta, M, m, n, 0);
+                qr[c][m * M + n] = q_weight(rho, delta, M, m, n, 1);
+                full[c] += qk[c][m * M + n];
+            }
+    }
+    unsigned char* status = (unsigned char*)malloc((size_t)W * H);
+    for (size_t q = 0; q < (size_t)W * H; ++q) status[q] = mask[q] ? ST_LOST : ST_KNOWN;
+    long long* share = (long long*)malloc(sizeof(long long) * (nmax + 1));
+    unsigned char* done = (unsigned char*)calloc(nmax + 1, 1);
+    for (int i = 0; i < nb; ++i) {
+        int c = bc[i], B = classes[3 * c], b = classes[3 * c + 1];
+        share[i] = window_share_sum(status, W, H, by[i] - b, bx[i] - b, B + 2 * b, qk[c], qr[c]);
+    }
+    for (int k = 0; k < nb; ++k) {
+        int best = -1;
+        for (int i = 0; i < nb; ++i) {
+            if (done[i]) continue;
+            /* share[i] / full[c_i] > share[best] / full[c_best], strictly:
+               the raster-earlier block keeps a tie */
+            if (best < 0 || (u128)share[i] * (u128)full[bc[best]] > (u128)share[best] * (u128)full[bc[i]])
+                best = i;
+        }
+        order[k] = best;
+        done[best] = 1;
+        int cb = bc[best], Bb = classes[3 * cb];
+        for (int y = by[best]; y < by[best] + Bb && y < H; ++y)
+            for (int x = bx[best]; x < bx[best] + Bb && x < W; ++x)
+                if (owner[(size_t)y * W + x] == best) status[(size_t)y * W + x] = ST_RECON;
+        for (int i = 0; i < nb; ++i) {
+            if (done[i]) continue;
+            int c = bc[i], B = classes[3 * c], b = classes[3 * c + 1];
+            int wy = by[i] - b, wx = bx[i] - b, M = B + 2 * b;
+            if (wy < by[best] + Bb && by[best] < wy + M && wx < bx[best] + Bb && bx[best] < wx + M)
+                share[i] = window_share_sum(status, W, H, wy, wx, M, qk[c], qr[c]);
+        }
+    }
+    for (int c = 0; c < n_classes; ++c) {
+        free(qk[c]);
+        free(qr[c]);
+    }
+    free(status);
+    free(share);
+    free(done);
+    free(owner);
+    free(by);
+    free(bx);
+    free(bc);
+    return nb;
+}
+
+/*
  * Whole image.  img: H*W values (row-major).  mask: 1 = lost.  out: H*W,
  * receives img with every lost pixel replaced.  order (may be NULL): a
  * permutation of 0..n_blocks-1 giving the processing order by raster index.

@@ -14,8 +14,10 @@ Contents
     side, processed as an independent image, cropped back to its core and
     merged.
   * :func:`dependencies` -- which earlier blocks a block must see finished in
-    raster order (a block reads the pixels of its support window, and writes
-    its own lost pixels).
+    raster order or in a given processing order (a block reads the pixels of
+    its support window, and writes its own lost pixels).
+  * :func:`priority_order` -- the optimised processing order (Sec. II),
+    reading R17.
 """
 from __future__ import annotations
 
@@ -81,6 +83,8 @@ def _bind(lib):
     lib.fse_oracle_plan.argtypes = [P(u8), i, i, P(i), i, P(i), P(i), P(i), i, P(i)]
     lib.fse_oracle_one_block.restype = d
     lib.fse_oracle_one_block.argtypes = [P(d), P(u8), i, i, i, i, i, i, i, d, d, d, P(d), P(i)]
+    lib.fse_oracle_priority_order.restype = i
+    lib.fse_oracle_priority_order.argtypes = [P(u8), i, i, P(i), i, d, d, P(i)]
     lib.fse_oracle_image.restype = i
     lib.fse_oracle_image.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(i), P(d), i, P(i), P(d),
                                      P(i), P(d), P(d)]
@@ -157,6 +161,25 @@ def plan(mask, classes):
                             _p(x, ctypes.c_int), _p(c, ctypes.c_int), n, _p(owner, ctypes.c_int))
     assert r == n
     return y[:n], x[:n], c[:n], owner
+
+
+def priority_order(mask, classes, rho=0.8, delta=0.5):
+    """Optimised processing order (Sec. II; reading R17 in fse_oracle.c): the
+    raster indices of the blocks in the order they are processed, each step
+    taking the remaining block whose window offers the largest share of
+    usable weight (ties to the raster-earlier block)."""
+    lib = _load()
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    H, W = mask.shape
+    ca = _classes_arr(classes)
+    n = len(plan(mask, classes)[0])
+    order = np.zeros(max(n, 1), np.int32)
+    r = lib.fse_oracle_priority_order(_p(mask, ctypes.c_uint8), W, H, _p(ca, ctypes.c_int), len(classes), rho,
+                                      delta, _p(order, ctypes.c_int))
+    if r < 0:
+        raise ValueError("oracle: bad arguments")
+    assert r == n
+    return order[:n]
 
 
 def image(img, mask, classes, rho=0.8, gamma=0.5, delta=0.5, order=None, trace=False):
@@ -305,15 +328,17 @@ def image_tiled(img, mask, classes, N: int, d: int, align: int, rho=0.8, gamma=0
 # Raster-order dependencies
 # ---------------------------------------------------------------------------
 
-def dependencies(mask, classes):
-    """For every raster block j, the earlier blocks i < j that must be finished
-    before j starts so that j sees the same window as in raster order: i owns
-    a lost pixel inside j's support window (j reads it as reconstructed), or j
-    owns a lost pixel inside i's window (i must read it before j writes it).
-    Brute force over pixels; meant for small images."""
+def dependencies(mask, classes, order=None):
+    """For every raster block j, the blocks i processed before j (raster
+    order, or the given processing order of raster indices) that must be
+    finished before j starts so that j sees the same window as in that order:
+    i owns a lost pixel inside j's support window (j reads it as
+    reconstructed), or j owns a lost pixel inside i's window (i must read it
+    before j writes it).  Brute force over pixels; meant for small images."""
     y, x, c, owner = plan(mask, classes)
     H, W = mask.shape
     n = len(y)
+    rank = np.arange(n) if order is None else np.argsort(np.asarray(order))
     win_owners = []
     for j in range(n):
         B, b, _ = classes[c[j]]
@@ -324,15 +349,16 @@ def dependencies(mask, classes):
     preds = [set() for _ in range(n)]
     for j in range(n):
         for i in win_owners[j]:
-            a, bb = (i, j) if i < j else (j, i)
+            a, bb = (i, j) if rank[i] < rank[j] else (j, i)
             preds[bb].add(a)
     return [sorted(p) for p in preds]
 
 
-def levels(preds):
-    """Longest-path level of every block (sources at level 0)."""
+def levels(preds, order=None):
+    """Longest-path level of every block (sources at level 0); blocks are
+    visited in raster order or in the given processing order."""
     lv = np.zeros(len(preds), np.int64)
-    for j in range(len(preds)):
+    for j in (range(len(preds)) if order is None else order):
         if preds[j]:
             lv[j] = 1 + max(lv[i] for i in preds[j])
     return lv

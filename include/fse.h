@@ -188,6 +188,32 @@ fse_status_t fse_extrapolate(const fse_image_t* image, const fse_mask_t* mask, c
 fse_status_t fse_extrapolate_batch(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
                                    const fse_params_t* p, fse_image_t* outs, void* stream);
 
+/*
+ * fse_extrapolate without allocation, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: tight serving loops,
+ * harnesses that forbid it).  Same arguments, results and errors as
+ * fse_extrapolate (results are identical); the device scratch of the call
+ * (FP64 working copy of reconstructed pixels, planning tables, flags and
+ * counters) lives in one fixed array of FSE_NOALLOC_SCRATCH_BYTES per device,
+ * held from the first call on that device until the process ends.  The call
+ * allocates no device or pinned host memory; the host planner reuses its
+ * own heap storage between calls.
+ *  - BUDGET when the call needs more scratch than the array holds (about
+ *    8 bytes per pixel of the image, or of every extended tile, plus ~48
+ *    bytes per processing block: a 1920x1080 image fits, 4 Mpixel do not);
+ *    nothing is enqueued then.
+ *  - All calls of this entry point in the process share the array of their
+ *    device: a call waits (on the host) until the previous call's kernels have
+ *    finished before it reuses the array, so calls on different streams are
+ *    serialised rather than overlapped.
+ *  - The time of the kernels is not measured (fse_last_stats reports
+ *    kernel_ms = 0; its device_error and n_degenerate words are read from the
+ *    array until the next call of this entry point on that device).
+ */
+#define FSE_NOALLOC_SCRATCH_BYTES (32ull << 20)
+fse_status_t fse_extrapolate_noalloc(const fse_image_t* image, const fse_mask_t* mask, const fse_params_t* p,
+                                     fse_image_t* out, void* stream);
+
 /* Statistics of the last extrapolate call made by this thread; waits for
  * that call's stream to finish its work. */
 fse_status_t fse_last_stats(fse_run_stats_t* st);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfse.so")
-SOURCES = ["fse_kernels.hip", "fse_api.cpp", "fse_plan.cpp", "fse_serve.cpp", "fse_graph.cpp"]
+SOURCES = ["fse_kernels.hip", "fse_api.cpp", "fse_plan.cpp", "fse_serve.cpp", "fse_graph.cpp", "fse_noalloc.hip"]
 HEADERS = ["fse_internal.h", "fse_plan.h", "fse_runtime.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -28,8 +28,16 @@ struct LastCall {
     int dev = -1;
     hipStream_t st = nullptr;
     uint64_t gen = 0;
+    // a call of fse_extrapolate_noalloc: its completion event and error words
+    hipEvent_t noalloc_done = nullptr;
+    const int32_t* noalloc_misc = nullptr;
 };
 thread_local LastCall g_last;
+
+void set_last_call_noalloc(const fse_run_stats_t& st, int dev, hipStream_t s, hipEvent_t done, const int32_t* misc) {
+    g_last_stats = st;
+    g_last = LastCall{dev, s, 0, done, misc};
+}
 
 static double now_ms() {
     using namespace std::chrono;
@@ -57,6 +65,15 @@ hipError_t DevBuf::ensure(size_t n, std::vector<void*>& retired) {
         return e;
     }
     cap = want;
+    return hipSuccess;
+}
+
+hipError_t Arena::take(DevBuf& b, size_t n) {
+    const size_t want = (std::max<size_t>(n, 1) + 255) & ~(size_t)255;
+    if (!dev || used > dev_cap || want > dev_cap - used) return hipErrorOutOfMemory;
+    b.p = dev + used;
+    b.cap = want;
+    used += want;
     return hipSuccess;
 }
 
@@ -222,7 +239,7 @@ static fse_status_t upload_tables(Workspace& ws, const std::vector<ClassCfg>& cl
                     h[off + m * c.M + n] = std::pow(rho, std::sqrt((m - ctr) * (m - ctr) + (n - ctr) * (n - ctr)));
             off += (size_t)c.M * c.M;
         }
-        hipError_t e = ws.tabs.ensure(total * sizeof(double), ws.retired_dev);
+        hipError_t e = ws.grow(ws.tabs, total * sizeof(double));
         if (e != hipSuccess) return from_hip(e);
         e = hipMemcpyAsync(ws.tabs.p, h.data(), total * sizeof(double), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return from_hip(e);
@@ -331,11 +348,24 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     fse_status_t s = FSE_OK;
     hipError_t e = hipSuccess;
     const double t0 = now_ms();
+    if (ws.arena) {
+        // every call carves its buffers afresh; the tables are uploaded again
+        ws.arena->used = 0;
+        for (DevBuf* b : {&ws.recon, &ws.owner, &ws.desc, &ws.lbox, &ws.done, &ws.tickets, &ws.jobs, &ws.misc,
+                          &ws.tabs})
+            *b = DevBuf{};
+        ws.tab_key.clear();
+        ws.host_mask = ws.arena->host_mask;
+        ws.host_mask_cap = ws.arena->host_mask_cap;
+        ws.stage = ws.arena->host_stage;
+        ws.stage_cap = ws.arena->host_stage_cap;
+    }
     // ---- masks to the host, regions, plans ---------------------------------
     std::vector<HostJob> jobs;
     std::vector<size_t> moff(n + 1, 0);
     for (int i = 0; i < n; ++i) moff[i + 1] = moff[i] + (size_t)images[i].width * images[i].height;
     if (ws.host_mask_cap < moff[n]) {
+        if (ws.arena) return FSE_ERR_BUDGET;
         // pinned memory grows with headroom; the old block is retired, not
         // freed (hipHostFree waits for the whole device)
         if (ws.host_mask) ws.retired_host.push_back(ws.host_mask);
@@ -446,15 +476,28 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
         n_cells += J.plan->owner.size();
         n_blk += J.plan->desc.size() / 4;
     }
-    auto grow = [&](DevBuf& b, size_t bytes) { return b.ensure(bytes, ws.retired_dev); };
-    if ((e = grow(ws.recon, n_pix * sizeof(double))) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.owner, std::max<size_t>(n_cells, 1) * 4)) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.desc, std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.lbox, std::max<size_t>(n_blk, 1) * 16)) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.done, std::max<size_t>(n_blk, 1) * 4)) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.tickets, (size_t)std::max<int64_t>(ntk, 1) * 8)) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.jobs, jobs.size() * sizeof(JobDev))) != hipSuccess) return from_hip(e);
-    if ((e = grow(ws.misc, 64)) != hipSuccess) return from_hip(e);
+    // (from the arena, a buffer that does not fit is a budget error: the
+    // arena's size is fixed)
+    auto grow = [&](DevBuf& b, size_t bytes) -> fse_status_t {
+        const hipError_t ge = ws.grow(b, bytes);
+        return ge == hipSuccess ? FSE_OK : ws.arena ? FSE_ERR_BUDGET : from_hip(ge);
+    };
+    if ((s = grow(ws.recon, n_pix * sizeof(double))) != FSE_OK) return s;
+    if ((s = grow(ws.owner, std::max<size_t>(n_cells, 1) * 4)) != FSE_OK) return s;
+    if ((s = grow(ws.desc, std::max<size_t>(n_blk, 1) * 16)) != FSE_OK) return s;
+    if ((s = grow(ws.lbox, std::max<size_t>(n_blk, 1) * 16)) != FSE_OK) return s;
+    if ((s = grow(ws.done, std::max<size_t>(n_blk, 1) * 4)) != FSE_OK) return s;
+    if ((s = grow(ws.tickets, (size_t)std::max<int64_t>(ntk, 1) * 8)) != FSE_OK) return s;
+    if ((s = grow(ws.jobs, jobs.size() * sizeof(JobDev))) != FSE_OK) return s;
+    if ((s = grow(ws.misc, 64)) != FSE_OK) return s;
+    if (ws.arena) {
+        // the tables (twiddles and rho^dist per class) take the arena's next range
+        size_t tab = 64 + 128;
+        for (auto& c : cls) tab += (size_t)c.M * c.M;
+        const size_t tab_bytes = (tab * sizeof(double) + 255) & ~(size_t)255;
+        if (ws.arena->used > ws.arena->dev_cap || tab_bytes > ws.arena->dev_cap - ws.arena->used)
+            return FSE_ERR_BUDGET;
+    }
 
     // host images of the tables in pinned staging memory, one upload each
     const size_t b_owner = std::max<size_t>(n_cells, 1) * 4, b_desc = std::max<size_t>(n_blk, 1) * 16,
@@ -463,6 +506,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
                  o_lbox = o_desc + ((b_desc + 255) & ~(size_t)255), o_tk = o_lbox + ((b_desc + 255) & ~(size_t)255),
                  o_jobs = o_tk + ((b_tk + 255) & ~(size_t)255), stage_bytes = o_jobs + b_jobs + 256;
     if (ws.stage_cap < stage_bytes) {
+        if (ws.arena) return FSE_ERR_BUDGET;
         if (ws.stage) ws.retired_host.push_back(ws.stage);
         ws.stage = nullptr;
         ws.stage_cap = 0;
@@ -761,6 +805,19 @@ fse_status_t fse_last_stats(fse_run_stats_t* st) {
             if (it != g_ws.end() && it->second->gen == g_last.gen) {
                 ws = it->second.get();
                 lk = std::unique_lock<std::mutex>(ws->mu);
+            }
+        }
+        if (g_last.noalloc_done) {
+            // the no-allocation entry point: its error words sit in the scratch
+            // (until the next such call on that device)
+            hipError_t e = hipEventSynchronize(g_last.noalloc_done);
+            if (e != hipSuccess) return from_hip(e);
+            int32_t misc[4] = {0, 0, 0, 0};
+            if (hipMemcpy(misc, g_last.noalloc_misc, sizeof(misc), hipMemcpyDeviceToHost) == hipSuccess) {
+                g_last_stats.device_error = misc[0];
+                int64_t deg = 0;
+                std::memcpy(&deg, misc + 2, sizeof(deg));
+                g_last_stats.n_degenerate = deg;
             }
         }
         if (ws) {

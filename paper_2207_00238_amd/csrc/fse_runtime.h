@@ -40,6 +40,20 @@ struct DevBuf {
     void release();
 };
 
+// Fixed storage for a workspace that must not allocate: device buffers are
+// carved in call order from one device range (reset at every call), and the
+// host staging buffers are fixed arrays.  A call that needs more than a range
+// holds fails with FSE_ERR_BUDGET before anything is enqueued.
+struct Arena {
+    unsigned char* dev = nullptr;  // device address of the range
+    size_t dev_cap = 0, used = 0;
+    uint8_t* host_mask = nullptr;  // mask read-back
+    size_t host_mask_cap = 0;
+    uint8_t* host_stage = nullptr;  // planning tables before upload
+    size_t host_stage_cap = 0;
+    hipError_t take(DevBuf& b, size_t n);
+};
+
 // Everything one extrapolation call needs on the device.  Calls that use the
 // same stream share one workspace and are serialised by its mutex.
 struct Workspace {
@@ -59,6 +73,9 @@ struct Workspace {
     // host planning state per job, reused between calls
     std::deque<RegionPlan> plans;
     std::vector<PlanScratch> plan_scratch;
+    Arena* arena = nullptr;  // set: every buffer comes from the arena (nothing is allocated or freed)
+    // a device buffer of at least n bytes: grown (allocating), or carved from the arena
+    hipError_t grow(DevBuf& b, size_t n) { return arena ? arena->take(b, n) : b.ensure(n, retired_dev); }
     void free_all();
 };
 
@@ -83,6 +100,8 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
                            const fse_params_t* p, const fse_image_t* outs, const std::vector<ClassCfg>& cls,
                            hipStream_t st, Prepared& P);
 fse_status_t launch_prepared(Workspace& ws, Prepared& P, hipStream_t st, bool timed);
+// record a call of fse_extrapolate_noalloc as this thread's last call
+void set_last_call_noalloc(const fse_run_stats_t& st, int dev, hipStream_t s, hipEvent_t done, const int32_t* misc);
 // statistics of this thread's last call as planned on the host (no device wait)
 void fse_last_stats_nowait(fse_run_stats_t* st);
 // The stream's workspace on the current device, returned with its mutex

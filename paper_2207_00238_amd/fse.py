@@ -33,8 +33,10 @@ EXPORTED = [
     "fse_status_string", "fse_params_default", "fse_plan_tiles", "fse_extrapolate", "fse_extrapolate_batch",
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
     "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy", "fse_plan_stats",
-    "fse_autotune", "fse_plan_tiles_vertical", "fse_serve_cancel",
+    "fse_autotune", "fse_plan_tiles_vertical", "fse_serve_cancel", "fse_extrapolate_noalloc",
 ]
+
+FSE_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class fse_image_t(ctypes.Structure):
@@ -106,6 +108,9 @@ def lib():
         L.fse_plan_tiles_vertical.argtypes = [ctypes.c_int32] * 5 + [P(fse_tile_t)]
         L.fse_extrapolate.restype = st
         L.fse_extrapolate.argtypes = [P(fse_image_t), P(fse_mask_t), P(fse_params_t), P(fse_image_t), ctypes.c_void_p]
+        L.fse_extrapolate_noalloc.restype = st
+        L.fse_extrapolate_noalloc.argtypes = [P(fse_image_t), P(fse_mask_t), P(fse_params_t), P(fse_image_t),
+                                              ctypes.c_void_p]
         L.fse_extrapolate_batch.restype = st
         L.fse_extrapolate_batch.argtypes = [ctypes.c_int32, P(fse_image_t), P(fse_mask_t), P(fse_params_t),
                                             P(fse_image_t), ctypes.c_void_p]
@@ -210,6 +215,13 @@ def fse_extrapolate(image, mask, params: fse_params_t, out, stream=None) -> None
     im, mk, ot = _image(image), _mask(mask), _image(out)
     check(lib().fse_extrapolate(ctypes.byref(im), ctypes.byref(mk), ctypes.byref(params), ctypes.byref(ot),
                                 _stream(stream)), "fse_extrapolate")
+
+
+def fse_extrapolate_noalloc(image, mask, params: fse_params_t, out, stream=None) -> None:
+    """fse_extrapolate with the library's fixed device scratch (no allocation)."""
+    im, mk, ot = _image(image), _mask(mask), _image(out)
+    check(lib().fse_extrapolate_noalloc(ctypes.byref(im), ctypes.byref(mk), ctypes.byref(params), ctypes.byref(ot),
+                                        _stream(stream)), "fse_extrapolate_noalloc")
 
 
 def fse_extrapolate_batch(images, masks, params: fse_params_t, outs, stream=None) -> None:

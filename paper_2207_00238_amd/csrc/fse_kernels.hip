@@ -121,20 +121,24 @@ __device__ __forceinline__ bool boxes_meet(int ay0, int ax0, int ay1, int ax1, i
     return ay0 < by1 && by0 < ay1 && ax0 < bx1 && bx0 < ax1;
 }
 
-// LDS layout.  The area holds w*s (M x (M+1)), kept from before the
+// LDS layout.  M = 32: the area holds w*s (M x (M+1)), kept from before the
 // dependency wait until the DFT of w*s after it, followed by a region that
 // first holds w (M x (M+1)) and then the weight spectrum for the K steps
-// (M = 32: (32 + kWrapRows) x 32 complex, rows 0 .. kWrapRows-1 repeated
-// after row 31; M = 64: 64 x 64 complex).  The coefficient list of the K
-// steps takes the part of the area that the steps no longer read.  Sized for
-// M = 32 (32 KB with the head) or, when a launch has M = 64 blocks, for
-// M = 64 (97 KB).
+// ((32 + kWrapRows) x 32 complex, rows 0 .. kWrapRows-1 repeated after row
+// 31); the coefficient list of the K steps takes the part of the area that
+// the steps no longer read (32 KB with the head).  M = 64: w*s and w in two
+// areas of 64 x 65; the weight spectrum (64 x 64 complex) stays in registers
+// from its DFT (before the wait) until the DFT of w*s has read both areas,
+// and is then written over them; the coefficient list follows (73 KB with
+// the head, so that two blocks share a CU).
 constexpr int kMaxK = 256;
 // A lane's four elements of one row tile lie on rows base + ROWR r (r < 4,
 // ROWR <= 4 rows): with the base reduced mod 32 they stay below 32 + 12.
 constexpr int kWrapRows = 12;
 constexpr int kBufDoubles32 = 32 * 33 + (32 + kWrapRows) * 32 * 2;  // w*s, then the weight spectrum
-constexpr int kBufDoubles64 = 64 * 65 + 64 * 64 * 2;      // w*s, then the weight spectrum
+// M = 64: w*s and w in two areas of 64 x 65, the weight spectrum written over
+// both once the DFT of w*s has read them, then the coefficient list
+constexpr int kBufDoubles64 = 2 * 64 * 65 + 2 * kMaxK + kMaxK / 2;
 
 struct SharedHead {
     double twc32[32], tws32[32];
@@ -160,6 +164,7 @@ struct Shared64 {
     double buf[kBufDoubles64];
 };
 static_assert(sizeof(Shared32) <= 32768, "five 32 x 32 blocks per CU");
+static_assert(2 * sizeof(Shared64) <= 160 * 1024, "two blocks of launches with 64 x 64 windows per CU");
 
 // Unsigned 32-bit maximum over a wave64 with DPP; the result is valid in
 // lane 63.  Non-negative doubles order like their bit patterns, so the high
@@ -390,18 +395,23 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // delta rho^dist), or lost otherwise (0) -- fixed by the mask and the plan,
     // so the weights, W0, the known part of w*s and the weight spectrum are
     // formed before the dependency wait; only the reconstructed values wait.
-    T* Xs = reinterpret_cast<T*>(buf);  // w * s, [m][n] stride LD
-    T* Wd = Xs + M * LD;                // weight spectrum [DUP ? M + kWrapRows : M][M] complex
-    T* Xw = Wd;                         // w, staged where the weight spectrum goes
+    // M = 64 keeps the weight spectrum in registers until both staged areas
+    // have been read (see the LDS layout above)
+    constexpr bool WREG = (M == 64);
+    T* Xs = reinterpret_cast<T*>(buf);           // w * s, [m][n] stride LD
+    T* Wd = WREG ? Xs : Xs + M * LD;             // weight spectrum [DUP ? M + kWrapRows : M][M] complex
+    T* Xw = WREG ? Xs + M * LD : Wd;             // w (M = 32: staged where the weight spectrum goes)
     // coefficient list of the K steps (real parts, imaginary parts, spectrum
-    // indices), written during the steps and read by the synthesis: in FP64
-    // over w*s, which the steps no longer read; in FP32 after the weight
-    // spectrum, where the buffer (sized for FP64) is free
+    // indices), written during the steps and read by the synthesis: M = 32
+    // in FP64 over w*s, which the steps no longer read, in FP32 after the
+    // weight spectrum, where the buffer (sized for FP64) is free; M = 64
+    // after the two staged areas
     constexpr int kWdRows = DUP ? M + kWrapRows : M;
-    static_assert(F64 ? 2 * kMaxK + kMaxK / 2 <= M * LD
-                      : (M * LD + kWdRows * M * 2) / 2 + 2 * kMaxK + kMaxK / 2 <= (M == 32 ? kBufDoubles32 : kBufDoubles64),
+    static_assert(WREG ? (2 * M * LD + 2 * kMaxK + kMaxK / 2 <= kBufDoubles64 && M * M * 2 * sizeof(T) <= 2 * M * LD * sizeof(double))
+                       : F64 ? 2 * kMaxK + kMaxK / 2 <= M * LD
+                             : (M * LD + kWdRows * M * 2) / 2 + 2 * kMaxK + kMaxK / 2 <= kBufDoubles32,
                   "coefficient list inside the buffer");
-    double* const clist = F64 ? buf : reinterpret_cast<double*>(Wd + kWdRows * M * 2);
+    double* const clist = WREG ? buf + 2 * M * LD : F64 ? buf : reinterpret_cast<double*>(Wd + kWdRows * M * 2);
     double* const car = clist;
     double* const cai = clist + kMaxK;
     int32_t* const cidx = reinterpret_cast<int32_t*>(clist + 2 * kMaxK);
@@ -553,7 +563,118 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     }
     };
 
-    dft(1);  // weight spectrum, before the wait
+    // M = 64: the DFT streams over the row tiles kt of the first-stage product
+    // T = X F -- each tile (kt, tj) is formed and at once contracted into
+    // the wave's output tiles (its share of the second stage's sum runs over
+    // k in tile kt) -- so only one tile of T is held at a time; the outputs
+    // go to registers: the weight spectrum (held until both staged areas
+    // have been read) or R
+    T wrr[WREG ? EPT : 1], wri[WREG ? EPT : 1];
+    auto dft_stream = [&](const int inp) {
+        int li = lane & 15, lk = lane >> 4;
+        asm volatile("" : "+v"(li), "+v"(lk));
+        acc4 o_re[NTI][NTJ], o_im[NTI][NTJ];
+#pragma unroll
+        for (int ci_ = 0; ci_ < NTI; ++ci_)
+#pragma unroll
+            for (int cj = 0; cj < NTJ; ++cj) {
+                o_re[ci_][cj] = acc4{0, 0, 0, 0};
+                o_im[ci_][cj] = acc4{0, 0, 0, 0};
+            }
+        if (!active) return;
+        const T* X = inp ? Xw : Xs;
+#pragma unroll
+        for (int kt = 0; kt < TM::TL; ++kt) {
+            // opaque per tile: the twiddles (the same for every kt) are read
+            // again for each tile instead of being held across all four
+            asm volatile("" : "+v"(li), "+v"(lk));
+#pragma unroll
+            for (int cj = 0; cj < NTJ; ++cj) {
+                const int tj = tj0 + cj;
+                acc4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+                if constexpr (PREC == kPrecBF16x3) {
+#pragma unroll
+                    for (int kk = 0; kk < KB; ++kk) {
+                        float av[4], bc[4], bs[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = kk * 16 + 4 * lk + q;
+                            av[q] = X[(kt * 16 + li) * LD + k];
+                            const int p = (k * (tj * 16 + li)) & MASK;
+                            bc[q] = (float)twc[p];
+                            bs[q] = -(float)tws[p];
+                        }
+                        cr = mfma_step3(av, bc, cr);
+                        ci = mfma_step3(av, bs, ci);
+                    }
+#pragma unroll
+                    for (int ci_ = 0; ci_ < NTI; ++ci_) {
+                        const int ti_o = ti0 + ci_;
+                        float c[4], sn[4], nsn[4], bre[4], bim[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int k = kt * 16 + 4 * lk + q;
+                            const int p = ((ti_o * 16 + li) * k) & MASK;
+                            c[q] = (float)twc[p];
+                            sn[q] = (float)tws[p];
+                            nsn[q] = -sn[q];
+                            bre[q] = cr[q];
+                            bim[q] = ci[q];
+                        }
+                        o_re[ci_][cj] = mfma_step3(c, bre, o_re[ci_][cj]);
+                        o_re[ci_][cj] = mfma_step3(sn, bim, o_re[ci_][cj]);
+                        o_im[ci_][cj] = mfma_step3(c, bim, o_im[ci_][cj]);
+                        o_im[ci_][cj] = mfma_step3(nsn, bre, o_im[ci_][cj]);
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KK; ++kk) {
+                        const T av = X[(kt * 16 + li) * LD + kk * 4 + lk];
+                        const int p = ((kk * 4 + lk) * (tj * 16 + li)) & MASK;
+                        cr = mfma_step(av, (T)twc[p], cr);
+                        ci = mfma_step(av, (T)(-tws[p]), ci);
+                    }
+#pragma unroll
+                    for (int ci_ = 0; ci_ < NTI; ++ci_) {
+                        const int ti_o = ti0 + ci_;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            // contraction index held by this lane in accumulator q of tile kt
+                            const int kk = kt * 4 + q;
+                            const int k = F64 ? (kk * 4 + lk) : ((kk >> 2) * 16 + 4 * lk + (kk & 3));
+                            const int p = ((ti_o * 16 + li) * k) & MASK;
+                            const T c = (T)twc[p], sn = (T)tws[p];
+                            o_re[ci_][cj] = mfma_step(c, cr[q], o_re[ci_][cj]);
+                            o_re[ci_][cj] = mfma_step(sn, ci[q], o_re[ci_][cj]);
+                            o_im[ci_][cj] = mfma_step(c, ci[q], o_im[ci_][cj]);
+                            o_im[ci_][cj] = mfma_step((T)(-sn), cr[q], o_im[ci_][cj]);
+                        }
+                    }
+                }
+            }
+        }
+        // element order within a lane = increasing spectrum index
+#pragma unroll
+        for (int ci_ = 0; ci_ < NTI; ++ci_)
+#pragma unroll
+            for (int cj = 0; cj < NTJ; ++cj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = (ci_ * 4 + r) * NTJ + cj;
+                    if (inp == 1) {
+                        wrr[e] = o_re[ci_][cj][r];
+                        wri[e] = o_im[ci_][cj][r];
+                    } else {
+                        rr[e] = o_re[ci_][cj][r];
+                        ri[e] = o_im[ci_][cj][r];
+                    }
+                }
+    };
+
+    if constexpr (WREG)
+        dft_stream(1);  // weight spectrum into registers, before the wait
+    else
+        dft(1);  // weight spectrum, before the wait
 
     // ---- wait for the earlier blocks this block depends on, then add their
     // reconstructed values to w*s
@@ -574,7 +695,26 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         }
     }
     __syncthreads();
-    dft(0);  // R
+    if constexpr (WREG) {
+        dft_stream(0);  // R
+        __syncthreads();  // both staged areas read: the weight spectrum takes them
+        if (active) {
+            int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+            for (int ci_ = 0; ci_ < NTI; ++ci_)
+#pragma unroll
+                for (int cj = 0; cj < NTJ; ++cj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int e = (ci_ * 4 + r) * NTJ + cj;
+                        const int k = (ti0 + ci_) * 16 + (F64 ? (lk + 4 * r) : (4 * lk + r)), l = (tj0 + cj) * 16 + li;
+                        Wd[(k * M + l) * 2] = wrr[e];
+                        Wd[(k * M + l) * 2 + 1] = wri[e];
+                    }
+        }
+    } else {
+        dft(0);  // R
+    }
     __syncthreads();
 
     // ---- K greedy steps ----------------------------------------------------
@@ -799,7 +939,12 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk)
 // WIDE: the launch holds M = 64 blocks (the shared area is sized for them and
 // each block branches on its window size).
 template <int NW, int PREC, bool WIDE>
-__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 4 : 1) k_fse_blocks(LaunchArgs a, int ticket_base) {
+// Occupancy (the second bound counts waves per SIMD): the 4-wave 32 x 32
+// kernel holds four blocks per CU (128 VGPRs); the FP64 kernel of launches
+// with 64 x 64 windows two (eight waves each, so four per SIMD: 128 VGPRs;
+// 73 KB of LDS each).
+__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) || (WIDE && PREC == 0) ? 4 : 1)
+    k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SharedHead& H = *reinterpret_cast<SharedHead*>(smem_raw);
     double* buf = reinterpret_cast<double*>(smem_raw + sizeof(SharedHead));

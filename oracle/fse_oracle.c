@@ -41,6 +41,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ST_KNOWN 0
 #define ST_LOST 1
@@ -473,6 +476,38 @@ int fse_oracle_priority_order(const unsigned char* mask, int W, int H, const int
 }
 
 /*
+ * One block of the whole-image process: its window from the current state,
+ * the greedy fit, and the model written into the lost pixels it owns (their
+ * status becomes reconstructed).  cls = (B, border, K).  sel/ar/ai receive
+ * the K steps; et/itp (may be NULL) the top energies.  Returns W0.
+ */
+static double run_block(int bi, int y0, int x0, const int* cls, const int* owner, double* out,
+                        unsigned char* status, int W, int H, double rho, double gamma, double delta, int* sel,
+                        double* ar, double* ai, double* et, int* itp) {
+    int B = cls[0], b = cls[1], K = cls[2];
+    int M = B + 2 * b;
+    int wy = y0 - b, wx = x0 - b;
+    double* w = (double*)calloc((size_t)M * M, sizeof(double));
+    double* s = (double*)calloc((size_t)M * M, sizeof(double));
+    window_of(out, status, W, H, wy, wx, M, rho, delta, w, s);
+    double W0 = fse_oracle_block(M, s, NULL, w, K, gamma, sel, ar, ai, NULL, et, itp);
+    for (int m = 0; m < M; ++m)
+        for (int n = 0; n < M; ++n) {
+            int y = wy + m, x = wx + n;
+            if (y < 0 || y >= H || x < 0 || x >= W) continue;
+            size_t q = (size_t)y * W + x;
+            if (owner[q] != bi) continue;
+            double gr = 0.0, gi = 0.0;
+            if (W0 > 0.0) synth_at(M, K, sel, ar, ai, m, n, &gr, &gi);
+            out[q] = gr;
+            status[q] = ST_RECON;
+        }
+    free(w);
+    free(s);
+    return W0;
+}
+
+/*
  * Whole image.  img: H*W values (row-major).  mask: 1 = lost.  out: H*W,
  * receives img with every lost pixel replaced.  order (may be NULL): a
  * permutation of 0..n_blocks-1 giving the processing order by raster index.
@@ -505,30 +540,14 @@ int fse_oracle_image(const double* img, const unsigned char* mask, int W, int H,
     for (int oi = 0; oi < nb; ++oi) {
         int bi = order ? order[oi] : oi;
         int c = blk_c[bi];
-        int B = classes[3 * c], b = classes[3 * c + 1], K = classes[3 * c + 2];
-        int M = B + 2 * b;
-        int wy = blk_y[bi] - b, wx = blk_x[bi] - b;
-        double* w = (double*)calloc((size_t)M * M, sizeof(double));
-        double* s = (double*)calloc((size_t)M * M, sizeof(double));
-        window_of(out, status, W, H, wy, wx, M, rho, delta, w, s);
+        int K = classes[3 * c + 2];
         int* sel = (int*)malloc(sizeof(int) * K);
         double* ar = (double*)malloc(sizeof(double) * K);
         double* ai = (double*)malloc(sizeof(double) * K);
         double* et = (double*)malloc(sizeof(double) * K * TOPN);
         int* itp = (int*)malloc(sizeof(int) * K * TOPN);
-        double W0 = fse_oracle_block(M, s, NULL, w, K, gamma, sel, ar, ai, NULL,
-                                     trace_e ? et : NULL, trace_e ? itp : NULL);
-        for (int m = 0; m < M; ++m)
-            for (int n = 0; n < M; ++n) {
-                int y = wy + m, x = wx + n;
-                if (y < 0 || y >= H || x < 0 || x >= W) continue;
-                size_t q = (size_t)y * W + x;
-                if (owner[q] != bi) continue;
-                double gr = 0.0, gi = 0.0;
-                if (W0 > 0.0) synth_at(M, K, sel, ar, ai, m, n, &gr, &gi);
-                out[q] = gr;
-                status[q] = ST_RECON;
-            }
+        double W0 = run_block(bi, blk_y[bi], blk_x[bi], classes + 3 * c, owner, out, status, W, H, rho, gamma,
+                              delta, sel, ar, ai, trace_e ? et : NULL, trace_e ? itp : NULL);
         if (W0 <= 0.0) rc = -2;
         if (trace_w0) trace_w0[bi] = W0;
         for (int it = 0; it < K && it < Kmax; ++it) {
@@ -549,8 +568,6 @@ int fse_oracle_image(const double* img, const unsigned char* mask, int W, int H,
         free(ai);
         free(et);
         free(itp);
-        free(w);
-        free(s);
     }
     free(status);
     free(owner);
@@ -558,4 +575,98 @@ int fse_oracle_image(const double* img, const unsigned char* mask, int W, int H,
     free(blk_x);
     free(blk_c);
     return rc;
+}
+
+/*
+ * The raster-order extrapolation of fse_oracle_image, with the blocks of each
+ * dependency level run in parallel on the host's cores (OpenMP).  A block
+ * depends on an earlier block when either one owns a lost pixel inside the
+ * other's support window (the window reads it, the owner writes it); a
+ * block's level is one more than the largest level of the blocks it depends
+ * on.  The blocks of one level neither read nor write each other's pixels,
+ * so each block sees exactly the window it sees in raster order and the
+ * output is bitwise the same.  *n_levels and *n_threads receive the number of
+ * levels and the threads used.  Returns as fse_oracle_image.
+ */
+int fse_oracle_image_levels(const double* img, const unsigned char* mask, int W, int H, const int* classes,
+                            int n_classes, double rho, double gamma, double delta, double* out, int* n_levels,
+                            int* n_threads) {
+    if (W <= 0 || H <= 0 || n_classes <= 0) return -1;
+    int nb = fse_oracle_plan(mask, W, H, classes, n_classes, NULL, NULL, NULL, 0, NULL);
+    int nmax = nb < 0 ? -nb : nb;
+    int* blk_y = (int*)malloc(sizeof(int) * (nmax + 1));
+    int* blk_x = (int*)malloc(sizeof(int) * (nmax + 1));
+    int* blk_c = (int*)malloc(sizeof(int) * (nmax + 1));
+    int* owner = (int*)malloc(sizeof(int) * (size_t)W * H);
+    nb = fse_oracle_plan(mask, W, H, classes, n_classes, blk_y, blk_x, blk_c, nmax, owner);
+    /* levels in raster order.  Scanning block j's window finds every block
+       that owns a lost pixel in it: an earlier owner is a predecessor of j; a
+       later owner has j as a predecessor (j reads the pixel before the owner
+       writes it), and is raised above j now -- before its own turn, so every
+       level is final when its block's turn comes. */
+    int* level = (int*)calloc(nmax + 1, sizeof(int));
+    for (int pass = 0; pass < 2 * nb; ++pass) {
+        int j = pass / 2, later = pass % 2;
+        int c = blk_c[j];
+        int B = classes[3 * c], b = classes[3 * c + 1], M = B + 2 * b;
+        for (int m = 0; m < M; ++m)
+            for (int n = 0; n < M; ++n) {
+                int y = blk_y[j] - b + m, x = blk_x[j] - b + n;
+                if (y < 0 || y >= H || x < 0 || x >= W) continue;
+                int o = owner[(size_t)y * W + x];
+                if (o < 0 || o == j) continue;
+                if (!later && o < j && level[o] + 1 > level[j]) level[j] = level[o] + 1;
+                if (later && o > j && level[j] + 1 > level[o]) level[o] = level[j] + 1;
+            }
+    }
+    int nl = 0;
+    for (int j = 0; j < nb; ++j)
+        if (level[j] + 1 > nl) nl = level[j] + 1;
+    /* blocks grouped by level (counting sort, raster order within a level) */
+    int* start = (int*)calloc(nl + 2, sizeof(int));
+    int* byl = (int*)malloc(sizeof(int) * (nmax + 1));
+    for (int j = 0; j < nb; ++j) start[level[j] + 1]++;
+    for (int l = 0; l < nl; ++l) start[l + 1] += start[l];
+    int* fill = (int*)malloc(sizeof(int) * (nl + 1));
+    for (int l = 0; l <= nl; ++l) fill[l] = start[l];
+    for (int j = 0; j < nb; ++j) byl[fill[level[j]]++] = j;
+
+    unsigned char* status = (unsigned char*)malloc((size_t)W * H);
+    for (size_t q = 0; q < (size_t)W * H; ++q) {
+        out[q] = mask[q] ? 0.0 : img[q];
+        status[q] = mask[q] ? ST_LOST : ST_KNOWN;
+    }
+    int degenerate = 0, threads = 1;
+    for (int l = 0; l < nl; ++l) {
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : degenerate)
+        for (int t = start[l]; t < start[l + 1]; ++t) {
+            int bi = byl[t];
+            int c = blk_c[bi];
+            int K = classes[3 * c + 2];
+            int* sel = (int*)malloc(sizeof(int) * (K > 0 ? K : 1));
+            double* ar = (double*)malloc(sizeof(double) * (K > 0 ? K : 1));
+            double* ai = (double*)malloc(sizeof(double) * (K > 0 ? K : 1));
+            double W0 = run_block(bi, blk_y[bi], blk_x[bi], classes + 3 * c, owner, out, status, W, H, rho,
+                                  gamma, delta, sel, ar, ai, NULL, NULL);
+            degenerate |= (W0 <= 0.0);
+            free(sel);
+            free(ar);
+            free(ai);
+        }
+    }
+#ifdef _OPENMP
+    threads = omp_get_max_threads();
+#endif
+    if (n_levels) *n_levels = nl;
+    if (n_threads) *n_threads = threads;
+    free(status);
+    free(start);
+    free(byl);
+    free(fill);
+    free(level);
+    free(owner);
+    free(blk_y);
+    free(blk_x);
+    free(blk_c);
+    return degenerate ? -2 : nb;
 }

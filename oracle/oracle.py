@@ -6,7 +6,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 Contents
   * ctypes access to ``fse_oracle.c`` (FP64 Frequency Selective
     Extrapolation, Sec. II of the paper): :func:`image`, :func:`block`,
-    :func:`plan`.
+    :func:`plan`, and :func:`image_levels` (the same result with the blocks
+    of each dependency level run in parallel on the host's cores).
   * :func:`tiling` -- the paper's compact tiling, Algorithm 1 with
     eqs. (1)-(5), written from the equations in pure Python integers.
   * :func:`tiles_with_stripe` and :func:`image_tiled` -- the overlapping-tile
@@ -40,7 +41,7 @@ def build(force: bool = False) -> str:
     """Compile fse_oracle.c with gcc into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -85,6 +86,8 @@ def _bind(lib):
     lib.fse_oracle_one_block.argtypes = [P(d), P(u8), i, i, i, i, i, i, i, d, d, d, P(d), P(i)]
     lib.fse_oracle_priority_order.restype = i
     lib.fse_oracle_priority_order.argtypes = [P(u8), i, i, P(i), i, d, d, P(i)]
+    lib.fse_oracle_image_levels.restype = i
+    lib.fse_oracle_image_levels.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(d), P(i), P(i)]
     lib.fse_oracle_image.restype = i
     lib.fse_oracle_image.argtypes = [P(d), P(u8), i, i, P(i), i, d, d, d, P(i), P(d), i, P(i), P(d),
                                      P(i), P(d), P(d)]
@@ -219,6 +222,26 @@ def image(img, mask, classes, rho=0.8, gamma=0.5, delta=0.5, order=None, trace=F
     return out
 
 
+def image_levels(img, mask, classes, rho=0.8, gamma=0.5, delta=0.5):
+    """The raster-order result of :func:`image`, with the blocks of each
+    dependency level run in parallel on the host's cores (OpenMP; bitwise the
+    same output).  Returns (out, number of levels, threads used)."""
+    lib = _load()
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    H, W = img.shape
+    ca = _classes_arr(classes)
+    out = np.zeros((H, W))
+    nl = ctypes.c_int(0)
+    nt = ctypes.c_int(0)
+    rc = lib.fse_oracle_image_levels(_p(img, ctypes.c_double), _p(mask, ctypes.c_uint8), W, H,
+                                     _p(ca, ctypes.c_int), len(classes), rho, gamma, delta,
+                                     _p(out, ctypes.c_double), ctypes.byref(nl), ctypes.byref(nt))
+    if rc == -1:
+        raise ValueError("oracle: bad arguments")
+    return out, nl.value, nt.value
+
+
 # ---------------------------------------------------------------------------
 # Algorithm 1: compact tiling (Sec. III, eqs. (1)-(5))
 # ---------------------------------------------------------------------------
@@ -229,49 +252,40 @@ def _round_half_up(q: Fraction) -> int:
 
 
 def tiling(W: int, H: int, N: int):
-    """Tiles (x_T, y_T, w_T, h_T) of a W x H image into N tiles.
+    """Tiles (x_T, y_T, w_T, h_T) of a W x H image into N tiles, from
+    eqs. (1)-(5) of Sec. III.
 
-    Landscape is assumed (W >= H); otherwise the axes are swapped, tiled and
-    swapped back.  eq. (1) r = W / H; eq. (2) n_R = max(1, round(sqrt(N / r)));
-    eq. (3) n_C per row i (1-based): ceil(N / n_R) for i <= N mod n_R, else
-    floor; eq. (4) h_T = floor(H n_C / N) + floor(((H n_C) mod N) / n_R), the
-    last row taking the rest of the height (rows clipped at the image bottom,
-    see below); eq. (5) w_T per tile j (1-based):
-    ceil(W / n_C) for j <= W mod n_C, else floor.  Offsets accumulate.
-    sqrt(N / r) is rounded exactly: round(sqrt(q)) = k  iff
-    (k - 1/2)^2 <= q < (k + 1/2)^2.
+    Landscape is assumed (W >= H); a portrait image is tiled as its transpose.
+    Each equation gives one list: eq. (1) the aspect ratio r = W / H; eq. (2)
+    the number of rows n_R = max(1, round(sqrt(N / r))), the square root
+    rounded exactly (round(sqrt(q)) = k iff (k - 1/2)^2 <= q < (k + 1/2)^2,
+    halves up); eq. (3) the tiles n_C of every row i = 1..n_R (ceil(N / n_R)
+    while i <= N mod n_R, else floor); eq. (4) the height h_T of every row,
+    the last row taking what is left of H; eq. (5) the width w_T of every
+    tile j = 1..n_C of a row (ceil(W / n_C) while j <= W mod n_C, else
+    floor).  Offsets are the running sums of heights and widths.  For large
+    N the heights of eq. (4) can add up to more than H: rows are then cut at
+    the bottom edge, and rows past it are empty.
     """
     if W < H:
         return [(y, x, h, w) for (x, y, w, h) in tiling(H, W, N)]
-    r = Fraction(W, H)
-    q = Fraction(N) / r  # value under the square root
+    r = Fraction(W, H)                                           # eq. (1)
+    q = Fraction(N) / r
     k = 0
     while Fraction(2 * k + 1, 2) ** 2 <= q:
         k += 1
-    n_R = max(1, k)
+    n_R = max(1, k)                                              # eq. (2)
+    rows = range(1, n_R + 1)
+    n_C = [-(-N // n_R) if i <= N % n_R else N // n_R for i in rows]      # eq. (3)
+    h_T = [(H * c) // N + ((H * c) % N) // n_R for c in n_C]             # eq. (4)
+    y_T = [min(H, sum(h_T[:i])) for i in range(n_R)]  # offsets, cut at the bottom edge
+    h_T = [min(H, y + h) - y for y, h in zip(y_T, h_T)]
+    h_T[-1] = H - y_T[-1]  # the last row takes what is left
     tiles = []
-    y_T = 0
-    for i in range(1, n_R + 1):
-        if i <= N % n_R:
-            n_C = -(-N // n_R)
-        else:
-            n_C = N // n_R
-        h_T = (H * n_C) // N + ((H * n_C) % N) // n_R
-        if i == n_R:
-            h_T = H - y_T
-        # eq. (4) can overshoot H when N is large (the second term adds up to
-        # (N - 1) / n_R per row); rows are clipped at the image bottom, so
-        # rows past it are empty
-        h_T = max(0, min(h_T, H - y_T))
-        x_T = 0
-        for j in range(1, n_C + 1):
-            if j <= W % n_C:
-                w_T = -(-W // n_C)
-            else:
-                w_T = W // n_C
-            tiles.append((x_T, y_T, w_T, h_T))
-            x_T += w_T
-        y_T += h_T
+    for y, h, c in zip(y_T, h_T, n_C):
+        w_T = [-(-W // c) if j <= W % c else W // c for j in range(1, c + 1)]  # eq. (5)
+        x_T = [sum(w_T[:j]) for j in range(c)]
+        tiles += [(x, y, w, h) for x, w in zip(x_T, w_T)]
     return tiles
 
 
@@ -309,16 +323,19 @@ def tiles_with_stripe(W: int, H: int, N: int, d: int, align: int = 1, vertical: 
 
 
 def image_tiled(img, mask, classes, N: int, d: int, align: int, rho=0.8, gamma=0.5, delta=0.5,
-                vertical: bool = False):
+                vertical: bool = False, optimized_order: bool = False):
     """Overlapping-tile framework on the CPU: each extended tile is extrapolated
-    as an independent image, cropped to its core and merged (Sec. III)."""
+    as an independent image, cropped to its core and merged (Sec. III); with
+    ``optimized_order`` each tile in its own optimised processing order."""
     H, W = img.shape
     out = np.zeros((H, W))
     for (core, ext) in tiles_with_stripe(W, H, N, d, align, vertical):
         ex, ey, ew, eh = ext
         if ew <= 0 or eh <= 0:
             continue
-        sub = image(img[ey:ey + eh, ex:ex + ew], mask[ey:ey + eh, ex:ex + ew], classes, rho, gamma, delta)
+        sm = mask[ey:ey + eh, ex:ex + ew]
+        order = priority_order(sm, classes, rho, delta) if optimized_order else None
+        sub = image(img[ey:ey + eh, ex:ex + ew], sm, classes, rho, gamma, delta, order=order)
         cx, cy, cw, ch = core
         out[cy:cy + ch, cx:cx + cw] = sub[cy - ey:cy - ey + ch, cx - ex:cx - ex + cw]
     return out

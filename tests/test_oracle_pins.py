@@ -359,3 +359,25 @@ def test_pins_reject_a_planted_mistake(name, pin, old, new, tmp_path):
             assert _checker_error() > 1e-6, name
     # the real oracle passes the same pin
     assert _oblique_error(0.5, 100) < 1e-6 and _checker_error() < 1e-9
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_level_parallel_oracle_is_bitwise_the_raster_oracle(case):
+    # the host baseline that runs the blocks of each dependency level on all
+    # cores: same output, bit for bit, as the one-block-at-a-time raster pass
+    if case == 0:
+        wl = synth.workload("small")
+        img, mask, cls = wl.image, wl.mask, wl.classes
+    elif case == 1:
+        img = synth.synth_image(150, 93, seed=61, period_max=128.0)
+        mask = synth.mask_blocks_and_pixels(150, 93, 4, 0.3, 0.01, seed=62)
+        cls = ((4, 14, 40),)
+    else:
+        img = synth.synth_image(96, 80, seed=63, period_max=64.0)
+        mask = synth.mask_mixed(96, 80, seed=64, frac8=0.1, frac16=0.05, row_fraction=0.03)
+        cls = ((16, 24, 20), (8, 28, 20), (4, 14, 20))
+    a = O.image(img, mask, cls)
+    b, n_levels, threads = O.image_levels(img, mask, cls)
+    assert np.array_equal(a, b)
+    assert n_levels == O.levels(O.dependencies(mask, cls)).max() + 1
+    assert threads >= 1

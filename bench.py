@@ -27,6 +27,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import itertools
 import hashlib
 import json
 import os
@@ -37,6 +38,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_FP64_VECTOR_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+
+
+def progress(msg: str) -> None:
+    """One line per finished part of the run, on stderr (the JSON result is the
+    only line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def block_flops(M: int, K: int, B: int) -> float:
@@ -106,11 +113,21 @@ def cpu_baseline():
     msk = wl.mask[:crop[0], :crop[1]]
     nb = len(oracle.plan(msk, wl.classes)[0])
     t0 = time.perf_counter()
-    oracle.image(img, msk, wl.classes, rho=wl.rho, gamma=wl.gamma, delta=wl.recon_weight)
+    ref = oracle.image(img, msk, wl.classes, rho=wl.rho, gamma=wl.gamma, delta=wl.recon_weight)
     dt = time.perf_counter() - t0
+    # the same crop with the blocks of each dependency level on all host cores
+    t0 = time.perf_counter()
+    par, n_levels, threads = oracle.image_levels(img, msk, wl.classes, rho=wl.rho, gamma=wl.gamma,
+                                                 delta=wl.recon_weight)
+    dtp = time.perf_counter() - t0
     return {"value": nb / dt, "unit": "blocks/s", "cores": 1, "kind": "oracle",
             "sample": f"top-left {crop[1]}x{crop[0]} crop of the first 1920x1080 request ({nb} blocks, {dt:.1f} s, "
-                      f"single-threaded FP64 C oracle)"}
+                      f"single-threaded FP64 C oracle)",
+            "level_parallel": {"value": nb / dtp, "unit": "blocks/s", "cores": threads, "kind": "oracle",
+                               "sample": f"same crop, the blocks of each of its {n_levels} dependency levels run "
+                                         f"in parallel (OpenMP), {dtp:.1f} s",
+                               "speedup_vs_one_core": dt / dtp,
+                               "bitwise_equal_to_one_core": bool(np.array_equal(ref, par))}}
 
 
 def cpu_tile_framework(one_core_rate: float):
@@ -169,11 +186,12 @@ def main():
                     help="3840x2160 mixed-loss images for the tiled batch measurement (0 = skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-block comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-order", action="store_true", help="skip the optimised-processing-order request")
     ap.add_argument("--streams", type=int, default=4,
                     help="streams the timed batched steps rotate over (1 = one step at a time; with the "
                          "default four, plain streams still get hardware queues of their own)")
     ap.add_argument("--workgroups", type=int, default=0)
-    ap.add_argument("--block-waves", type=int, default=4)
+    ap.add_argument("--block-waves", type=int, default=0, help="wave64s per block (0 = autotuned among 1, 2, 4)")
     ap.add_argument("--tiles", type=str, default="64",
                     help="comma-separated tile counts for the tile-framework comparison ('' = none)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="length of the served Poisson stream (0 = skip)")
@@ -181,8 +199,10 @@ def main():
     ap.add_argument("--no-border-sweep", action="store_true",
                     help="skip the tile-border sweep (PSNR vs stripe width d at N = 32 tiles)")
     ap.add_argument("--serve-rate", type=float, default=16.0, help="requests per second of the served stream")
-    ap.add_argument("--serve-mixed-seconds", type=float, default=2.0,
+    ap.add_argument("--serve-mixed-seconds", type=float, default=60.0,
                     help="arrival window of the mixed-size served stream (0 = skip)")
+    ap.add_argument("--serve-mixed-below-seconds", type=float, default=8.0,
+                    help="arrival window of the same stream at 40 and 80 requests/s (0 = skip)")
     ap.add_argument("--serve-mixed-rate", type=float, default=200.0,
                     help="requests per second of the mixed-size served stream (sides 512..4096)")
     ap.add_argument("--only-uhd", action="store_true",
@@ -241,6 +261,7 @@ def main():
     st = fse.fse_last_stats()
     n_blocks = st["n_blocks"]
 
+    progress("warm-up and autotuning done")
     # serialised steps: each launch alone on the device (launch duration,
     # roofline and step latency are taken here)
     step_ms, kern_ms, plan_ms = [], [], []
@@ -260,6 +281,7 @@ def main():
     serial_outs = [o.clone() for o in outs]
     batched_out0 = serial_outs[0]
 
+    progress("serialised steps done")
     # pipelined steps: consecutive batches on `streams` streams (each with
     # its own workspace and outputs), so the host planning of a batch and the
     # launches of the batches before it run at the same time and the
@@ -276,22 +298,11 @@ def main():
 
         # grid for overlapping steps (untimed): the step-at-a-time choice
         # above need not be the best once several launches share the CUs
-        # Two interleaved rounds (every candidate once per round, so drift
-        # and order effects fall on all of them), ranked by their total time.
         p_pipe = params
-        if args.workgroups == 0:
-            cands = {wg: [0.0, fse.fse_params_default(**{**common, "workgroups": wg,
-                                                          "block_waves": params.block_waves})]
-                     for wg in dict.fromkeys([params.workgroups, 0, 768, 1024])}
-            for _ in range(2):
-                for c in cands.values():
-                    rotate(c[1], args.streams)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    rotate(c[1], 2 * args.streams)
-                    torch.cuda.synchronize()
-                    c[0] += time.perf_counter() - t0
-            p_pipe = min(cands.values(), key=lambda c: c[0])[1]
+        if args.workgroups == 0 and not args.no_autotune:
+            # the library's tuner for consecutive calls in flight (the waves per
+            # block fixed to the single-call choice)
+            p_pipe = fse.fse_autotune_overlapped(imgs, msks, params, outs, args.streams)
         rotate(p_pipe, args.streams)
         torch.cuda.synchronize()
         t_all = time.perf_counter()
@@ -327,7 +338,7 @@ def main():
                                f"{n_blocks} processing blocks per step, B={B} b={b} M={M} K={K}, rho={wl.rho}, "
                                f"gamma={wl.gamma}, exact raster semantics per request",
                    "schedule": f"one persistent dependency-driven launch per step, "
-                               f"{params.block_waves} waves/block, grid {params.workgroups or 'automatic'}"
+                               f"{params.block_waves or 4} waves/block, grid {params.workgroups or 'automatic'}"
                                + (" (autotuned)" if tuned else "")
                                + (f"; consecutive steps on {args.streams} streams, grid "
                                   f"{pipe['workgroups']}" if pipe else "")},
@@ -339,12 +350,13 @@ def main():
         "host_plan_ms": float(np.mean(plan_ms)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_VECTOR_TFLOPS, "traffic": traffic,
-                     "kernel": f"k_fse_blocks<{params.block_waves}>", "flops_per_block": flops,
+                     "kernel": f"k_fse_blocks<{params.block_waves or 4}>", "flops_per_block": flops,
                      # the same work over the overlapped timed steps (launches share the device there)
                      "achieved_overlapped": n_blocks * flops * args.steps / total / 1e12,
                      "frac_overlapped": n_blocks * flops * args.steps / total / 1e12 / MI355X_FP64_VECTOR_TFLOPS},
     }
 
+    progress("pipelined steps done")
     if args.only_batched:
         print(json.dumps(result), flush=True)
         return
@@ -365,6 +377,7 @@ def main():
     finally:
         fse.fse_plan_destroy(plan)
 
+    progress("graph replay done")
     # ---- one request alone ------------------------------------------------
     img, msk, out = imgs[0], msks[0], outs[0]
     fse.fse_extrapolate(img, msk, params, out, stream)
@@ -380,6 +393,12 @@ def main():
     result["single_request"] = {"value": nb1 / float(np.mean(times)), "unit": "blocks/s",
                                 "ms": float(np.mean(times)) * 1e3, "kernel_ms": s1["kernel_ms"],
                                 "blocks": nb1, "bitwise_equal_to_batched": bool(torch.equal(res_single, batched_out0))}
+
+    progress("single request done")
+    # ---- the optimised processing order (Sec. II) on the same request --------
+    if not args.no_order:
+        result["optimized_order"] = optimized_order(fse, torch, np, img, msk, common, wl, args.steps, res_single,
+                                                    s1, float(np.mean(times)))
 
     if args.tiles:
         m = torch.from_numpy(wl.mask).bool()
@@ -411,6 +430,7 @@ def main():
                                     "dpsnr_vs_whole_db": psnr(out.cpu()) - p_whole,
                                     "dssim_vs_whole": ssim(out.cpu().numpy(), wl.image) - s_whole})
 
+    progress("optimised order and tile framework done")
     # the time to compute a tiling (the paper times its tilings of 6024x4024
     # images): fse_plan_tiles through a bare ctypes call, mean over repeated
     # calls -- an upper bound, the call overhead included
@@ -427,12 +447,19 @@ def main():
     if args.tiles and not args.no_border_sweep:
         result["tile_border_sweep"] = border_sweep(fse, torch, np, img, msk, common, wl, p_whole, s_whole)
 
+    progress("tiling time and border sweep done")
     if args.uhd_images > 0:
         result["uhd_tiled_batch"] = uhd_batch(fse, torch, np, args.uhd_images, args.steps, args.streams)
 
+    progress("3840x2160 tiled batch done")
     if not args.no_precision_sweep:
-        result["precision_sweep"] = precision_sweep(fse, torch, np, img, msk, common, wl, K)
+        ws = synth.workload("small")
+        small = (torch.from_numpy(ws.image).to(dev), torch.from_numpy(ws.mask).to(dev))
+        result["precision_sweep"] = precision_sweep(fse, torch, np, common, [
+            ("128x128, 20% of 4x4 blocks lost", small[0], small[1], ws.image, ws.classes),
+            ("1920x1080, 25% of 4x4 blocks + 1% pixels lost", img, msk, wl.image, wl.classes)])
 
+    progress("precision sweep done")
     if args.serve_seconds > 0:
         # served launches hold one to a few requests: the automatic grid (sized
         # from each launch's own blocks per wavefront key), not the batch's
@@ -440,10 +467,18 @@ def main():
         result["served"] = serve_stream(fse, torch, np, imgs, msks, p_serve, args.serve_rate, args.serve_seconds,
                                         nb1, res_single)
 
+    progress("served 1080p stream done")
     if args.serve_mixed_seconds > 0:
         result["served_mixed"] = serve_mixed(fse, torch, np, common, args.serve_mixed_rate,
-                                             args.serve_mixed_seconds)
+                                             args.serve_mixed_seconds, plain_sample=40)
+        # below capacity: the same trace recipe at lower rates
+        result["served_mixed"]["below_capacity"] = [
+            {k: v for k, v in serve_mixed(fse, torch, np, common, r, args.serve_mixed_below_seconds).items()
+             if k in ("requests", "rate_hz", "seconds", "offered_blocks_per_s", "value", "p50_ms", "p99_ms",
+                      "drain_s")}
+            for r in (40.0, 80.0)] if args.serve_mixed_below_seconds > 0 else []
 
+    progress("served mixed-size streams done")
     if not args.no_plain:
         p_plain = fse.fse_params_default(schedule=fse.FSE_SCHED_PER_BLOCK, **common)
         torch.cuda.synchronize()
@@ -457,11 +492,47 @@ def main():
                            "bitwise_equal_to_batched": same}
         result["speedup_vs_plain"] = value / (nb1 / dt)
 
+    progress("plain path done")
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
         if not args.only_batched:
             result["cpu_baseline"]["tile_framework"] = cpu_tile_framework(result["cpu_baseline"]["value"])
     print(json.dumps(result), flush=True)
+
+
+def optimized_order(fse, torch, np, img, msk, common, wl, steps, res_raster, st_raster, t_raster):
+    """One 1080p request in the optimised processing order (FSE_ORDER_OPTIMIZED)
+    beside the same request in raster order: dependency levels of the two
+    DAGs, host planning and kernel time, end-to-end time, and the PSNR of
+    each against the pre-loss image."""
+    p = fse.fse_params_default(**{**common, "workgroups": 0, "order": fse.FSE_ORDER_OPTIMIZED})
+    out = torch.empty_like(img)
+    fse.fse_extrapolate(img, msk, p, out)
+    fse.fse_last_stats()
+    times, kern, plan = [], [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        fse.fse_extrapolate(img, msk, p, out)
+        s = fse.fse_last_stats()
+        times.append(time.perf_counter() - t0)
+        kern.append(s["kernel_ms"])
+        plan.append(s["host_plan_ms"])
+    if s["device_error"]:
+        raise RuntimeError("device dependency wait timed out")
+    m = torch.from_numpy(wl.mask).bool()
+    gt = torch.from_numpy(wl.image).double()
+
+    def psnr(x):
+        e = (x.double().clamp(0, 255) - gt)[m]
+        return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
+
+    return {"value": s["n_blocks"] / float(np.mean(times)), "unit": "blocks/s",
+            "ms": float(np.mean(times)) * 1e3, "kernel_ms": float(np.mean(kern)),
+            "host_plan_ms": float(np.mean(plan)), "levels": s["wavefront_keys"],
+            "psnr_db": psnr(out.cpu()), "raster": {"ms": t_raster * 1e3, "kernel_ms": st_raster["kernel_ms"],
+                                                  "host_plan_ms": st_raster["host_plan_ms"],
+                                                  "levels": st_raster["wavefront_keys"],
+                                                  "psnr_db": psnr(res_raster.cpu())}}
 
 
 def border_sweep(fse, torch, np, img, msk, common, wl, p_whole, s_whole):
@@ -576,48 +647,58 @@ def uhd_batch(fse, torch, np, n, steps, streams=1):
     return res
 
 
-def precision_sweep(fse, torch, np, img, msk, common, wl, K):
-    """FP32 and BF16x3 against the FP64 path on the first request: speed,
-    pixel error, PSNR change and the rate of blocks whose basis selections
-    leave the FP64 sequence (mirror choices of exactly tied pairs, which give
-    the same real output, are not counted)."""
-    M = 32
-    m = torch.from_numpy(wl.mask).bool()
-    gt = torch.from_numpy(wl.image).double()
+def precision_sweep(fse, torch, np, common, cases):
+    """FP32 and BF16x3 against the FP64 path (which the tests hold to the FP64
+    oracle within 1e-5) on each named workload: speed, pixel error, PSNR
+    change, the rate of blocks whose basis selections leave the FP64 sequence
+    (mirror choices of exactly tied pairs, which give the same real output,
+    are not counted), and whether the pixel part of the stated bar holds
+    (>= 99.9 % of lost pixels within 0.5, |dPSNR| <= 0.01 dB).  The tests
+    apply the full bar, with the oracle's energy gaps, to the 128 x 128
+    workload."""
+    rows = []
+    for (name, img, msk, gt_np, classes) in cases:
+        K = max(c[2] for c in classes)
+        M = classes[-1][0] + 2 * classes[-1][1]
+        m = torch.from_numpy(msk.cpu().numpy()).bool()
+        gt = torch.from_numpy(gt_np).double()
 
-    def psnr(x):
-        e = (x.double().clamp(0, 255) - gt)[m]
-        return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
+        def psnr(x):
+            e = (x.double().clamp(0, 255) - gt)[m]
+            return float(10 * torch.log10(255.0 ** 2 / (e * e).mean()))
 
-    def run(prec):
-        st0 = fse.fse_params_default(precision=prec, **common)
-        out = torch.empty_like(img)
-        fse.fse_extrapolate(img, msk, st0, out)
-        nb = fse.fse_last_stats()["n_blocks"]
-        sel = torch.full((nb, K), -1, dtype=torch.int32, device=img.device)
-        st0.trace_sel = sel.data_ptr()
-        st0.trace_stride = K
-        st0.trace_capacity = nb
-        t0 = time.perf_counter()
-        fse.fse_extrapolate(img, msk, st0, out)
-        s = fse.fse_last_stats()
-        dt = time.perf_counter() - t0
-        return out.cpu(), sel.cpu().numpy(), nb / dt, s["kernel_ms"]
+        def run(prec):
+            st0 = fse.fse_params_default(**{**common, "classes": classes, "precision": prec, "workgroups": 0})
+            out = torch.empty_like(img)
+            fse.fse_extrapolate(img, msk, st0, out)
+            nb = fse.fse_last_stats()["n_blocks"]
+            sel = torch.full((nb, K), -1, dtype=torch.int32, device=img.device)
+            st0.trace_sel = sel.data_ptr()
+            st0.trace_stride = K
+            st0.trace_capacity = nb
+            t0 = time.perf_counter()
+            fse.fse_extrapolate(img, msk, st0, out)
+            s = fse.fse_last_stats()
+            dt = time.perf_counter() - t0
+            return out.cpu(), sel.cpu().numpy(), nb / dt, s["kernel_ms"]
 
-    ref, sref, v64, k64 = run(0)
-    p64 = psnr(ref)
-    u, v = np.divmod(sref, M)
-    mirror = ((-u) % M) * M + ((-v) % M)
-    res = {"fp64": {"value": v64, "kernel_ms": k64}}
-    for name, prec in (("fp32", 1), ("bf16x3", 2)):
-        out, sel, val, km = run(prec)
-        d = (out.double() - ref.double()).abs()[m]
-        same = (sel == sref) | (sel == mirror)
-        bad = (~same).any(axis=1)
-        res[name] = {"value": val, "kernel_ms": km, "max_abs_dpixel": float(d.max()),
-                     "frac_le_half": float((d <= 0.5).double().mean()), "dpsnr_db": psnr(out) - p64,
-                     "selection_divergence_rate": float(bad.mean())}
-    return res
+        ref, sref, v64, k64 = run(0)
+        p64 = psnr(ref)
+        u, v = np.divmod(sref, M)
+        mirror = ((-u) % M) * M + ((-v) % M)
+        rows.append({"workload": name, "mode": "fp64", "value": v64, "kernel_ms": k64})
+        for mode, prec in (("fp32", 1), ("bf16x3", 2)):
+            out, sel, val, km = run(prec)
+            d = (out.double() - ref.double()).abs()[m]
+            same = (sel == sref) | (sel == mirror)
+            bad = (~same).any(axis=1)
+            frac = float((d <= 0.5).double().mean())
+            dpsnr = psnr(out) - p64
+            rows.append({"workload": name, "mode": mode, "value": val, "kernel_ms": km,
+                         "max_abs_dpixel": float(d.max()), "frac_le_half": frac, "dpsnr_db": dpsnr,
+                         "selection_divergence_rate": float(bad.mean()),
+                         "meets_pixel_bar": bool(frac >= 0.999 and abs(dpsnr) <= 0.01)})
+    return rows
 
 
 def serve_stream(fse, torch, np, imgs, msks, params, rate, seconds, blocks_per_req, ref0):
@@ -656,12 +737,22 @@ def serve_stream(fse, torch, np, imgs, msks, params, rate, seconds, blocks_per_r
             "bitwise_equal_to_alone": bool(torch.equal(outs[first0], ref0))}
 
 
-def serve_mixed(fse, torch, np, common, rate, seconds):
-    """Poisson arrivals of square requests with sides {512, 1024, 2048, 4096}
-    and two mask kinds (the serving trace of the input recipe) into the
-    server, at a rate above what the device can absorb: the achieved rate is
-    the saturation throughput and the latencies are queue-dominated.  Inputs
-    come from a pool of one image and mask per (side, kind)."""
+def serve_mixed(fse, torch, np, common, rate, seconds, pool_per_side=96, plain_sample=0):
+    """The serving workload: Poisson arrivals at ``rate`` over ``seconds`` of
+    square requests with sides {512, 1024, 2048, 4096} and two mask kinds
+    (the serving trace of the input recipe) into the continuous-batching
+    server.  Inputs come from a pool of one image and mask per (side, kind);
+    outputs from a pool of ``pool_per_side`` buffers per side, recycled as
+    requests finish: a request that arrives while every buffer of its side is
+    in use waits in arrival order for the next free one.  Latency runs from
+    the request's arrival (not its submission) to its completion on the host
+    clock, so waiting for a buffer counts as queueing.  Above capacity the
+    achieved rate is the saturation throughput and the latencies grow with
+    the backlog, which is reported once per second (requests arrived and not
+    finished).  With ``plain_sample`` > 0 the first requests of the trace are
+    also run one at a time through fse_extrapolate, the plain per-request
+    path."""
+    from collections import deque
     from paper_2207_00238_amd import synth
     dev = torch.device("cuda:0")
     trace = synth.poisson_trace(rate, seconds, seed=31)
@@ -672,37 +763,91 @@ def serve_mixed(fse, torch, np, common, rate, seconds):
             img, msk = synth.request_inputs(req)
             pool[key] = (torch.from_numpy(img).to(dev), torch.from_numpy(msk).to(dev))
     p = fse.fse_params_default(**{**common, "workgroups": 0})
-    outs = [torch.empty_like(pool[(r["side"], r["kind"])][0]) for r in trace]
+    sides = sorted({r["side"] for r in trace})
+    free = {sd: deque(torch.empty((sd, sd), dtype=torch.float32, device=dev) for _ in range(pool_per_side))
+            for sd in sides}
     torch.cuda.synchronize()
     srv = fse.fse_serve_create(hbm_budget_bytes=32 << 30, max_slots=4)
-    tickets = []
+    waiting = deque()      # arrived, no free output buffer yet
+    inflight = {}          # ticket -> (trace index, output buffer)
+    done_at = [None] * len(trace)
+    blocks = [0] * len(trace)
+    first_out = {}         # side -> output of the first request of that side (kept for the check below)
+    backlog = []
+    nxt = 0
+    t0 = time.perf_counter()
+    next_sample = 1.0
     try:
-        t0 = time.perf_counter()
-        for i, req in enumerate(trace):
+        while nxt < len(trace) or waiting or inflight:
             now = time.perf_counter() - t0
-            if req["t"] > now:
-                time.sleep(req["t"] - now)
-            im, mk = pool[(req["side"], req["kind"])]
-            tickets.append(fse.fse_serve_submit(srv, im, mk, p, outs[i]))
-        stats = [fse.fse_serve_wait(srv, tk, 600_000_000) for tk in tickets]
-        t_end = time.perf_counter()
+            while nxt < len(trace) and trace[nxt]["t"] <= now:
+                waiting.append(nxt)
+                nxt += 1
+            # submit in arrival order while buffers last (a request whose side
+            # has no free buffer holds back the ones behind it only of its side)
+            held = deque()
+            while waiting:
+                i = waiting.popleft()
+                sd = trace[i]["side"]
+                if free[sd]:
+                    out = free[sd].popleft()
+                    im, mk = pool[(sd, trace[i]["kind"])]
+                    inflight[fse.fse_serve_submit(srv, im, mk, p, out)] = (i, out)
+                else:
+                    held.append(i)
+            waiting = held
+            # requests finish roughly in submission order: poll the oldest few
+            for tk in list(itertools.islice(inflight, 48)):
+                fin, st = fse.fse_serve_poll(srv, tk)
+                if fin:
+                    i, out = inflight.pop(tk)
+                    done_at[i] = time.perf_counter() - t0
+                    blocks[i] = st["n_blocks"]
+                    sd = trace[i]["side"]
+                    if sd not in first_out:
+                        first_out[sd] = (i, out)  # not recycled: compared below
+                    else:
+                        free[sd].append(out)
+            if now >= next_sample:
+                backlog.append([round(now, 1), nxt - sum(d is not None for d in done_at)])
+                next_sample += 1.0
+                if len(backlog) % 15 == 0:
+                    progress(f"served stream at {rate:g}/s: {now:.0f} s, {backlog[-1][1]} requests waiting or running")
+            time.sleep(0.002)
+        t_end = time.perf_counter() - t0
     finally:
         fse.fse_serve_destroy(srv)
-    lat = np.array([s["t_done_ms"] - s["t_submit_ms"] for s in stats])
-    blocks = sum(s["n_blocks"] for s in stats)
-    # one request of each side against the same request alone
+    lat = np.array([(done_at[i] - trace[i]["t"]) * 1e3 for i in range(len(trace))])
+    total_blocks = sum(blocks)
+    # the first request of each side against the same request alone
     same = True
-    for side in sorted({r["side"] for r in trace}):
-        i = next(k for k, r in enumerate(trace) if r["side"] == side)
-        im, mk = pool[(trace[i]["side"], trace[i]["kind"])]
+    for sd, (i, out) in first_out.items():
+        im, mk = pool[(sd, trace[i]["kind"])]
         o = torch.empty_like(im)
         fse.fse_extrapolate(im, mk, p, o)
         torch.cuda.synchronize()
-        same = same and bool(torch.equal(o, outs[i]))
-    return {"requests": len(trace), "rate_hz": rate, "seconds": seconds, "sides": [512, 1024, 2048, 4096],
-            "offered_blocks_per_s": blocks / seconds, "value": blocks / (t_end - t0), "unit": "blocks/s",
-            "drain_s": t_end - t0, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "bitwise_equal_to_alone": same}
+        same = same and bool(torch.equal(o, out))
+    res = {"requests": len(trace), "rate_hz": rate, "seconds": seconds, "sides": sides,
+           "offered_blocks_per_s": total_blocks / seconds, "value": total_blocks / t_end, "unit": "blocks/s",
+           "drain_s": t_end, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "latency_from": "arrival", "output_buffers_per_side": pool_per_side,
+           "backlog_requests_per_s": backlog[::max(1, len(backlog) // 20)],
+           "bitwise_equal_to_alone": same}
+    if plain_sample > 0:
+        # the plain per-request path: the first requests one at a time
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        nbp = 0
+        for r in trace[:plain_sample]:
+            im, mk = pool[(r["side"], r["kind"])]
+            o = free[r["side"]][0] if free[r["side"]] else torch.empty_like(im)
+            fse.fse_extrapolate(im, mk, p, o)
+            nbp += fse.fse_last_stats()["n_blocks"]
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - tp
+        res["plain_per_request"] = {"value": nbp / dtp, "unit": "blocks/s", "requests": plain_sample,
+                                    "note": "the trace's first requests, each alone through fse_extrapolate"}
+    return res
 
 
 if __name__ == "__main__":

@@ -68,6 +68,16 @@ typedef int32_t fse_status_t;
 #define FSE_TILED 1          /* compact tiling, Algorithm 1 (Sec. III) */
 #define FSE_TILED_VERTICAL 2 /* N full-height stripes: the baseline the compact tiling improves on */
 
+/* processing order of the blocks (each order is executed exactly: a block sees
+ * the pixels of every block before it in the order as reconstructed) */
+#define FSE_ORDER_RASTER 0    /* raster order of the blocks' top-left corners */
+#define FSE_ORDER_OPTIMIZED 1 /* optimised order, Sec. II: large lost areas close from their margins
+                                 inwards; each step takes the remaining block whose support window offers
+                                 the largest share of usable weight (its sum of window weights under the
+                                 current statuses over that of a fully known window; the weights rounded
+                                 to multiples of 2^-30 so that shares compare exactly), ties to the
+                                 raster-earlier block.  Fixed by the mask alone, planned on the host. */
+
 #define FSE_MAX_CLASSES 3
 
 /* A device image: float32 values, `pitch` elements between rows. */
@@ -112,8 +122,11 @@ typedef struct {
  * block grid anchored at its own top-left corner: a d that is not a
  * multiple of align shifts that grid against the image's.
  * trace_sel (device, may be NULL): receives the selected index u*M+v of
- * every step of every block, at [raster_block_index * trace_stride + step];
- * trace_capacity bounds the number of blocks traced.
+ * every step of every block, at [block_index * trace_stride + step], the
+ * block index being the block's position in the processing order (raster
+ * order unless `order` says otherwise); trace_capacity bounds the number of
+ * blocks traced.
+ * order: FSE_ORDER_RASTER or FSE_ORDER_OPTIMIZED.
  */
 typedef struct {
     int32_t n_classes;
@@ -128,6 +141,7 @@ typedef struct {
     int32_t* trace_sel;
     int32_t trace_stride;
     int64_t trace_capacity;
+    int32_t order; /* FSE_ORDER_* */
 } fse_params_t;
 
 /* Counters of the last fse_extrapolate* call on the calling thread. */
@@ -218,16 +232,35 @@ fse_status_t fse_extrapolate_noalloc(const fse_image_t* image, const fse_mask_t*
  * that call's stream to finish its work. */
 fse_status_t fse_last_stats(fse_run_stats_t* st);
 
-/* Schedule autotuner: runs the given batch (outputs written to outs) with
- * wave64s per block in {2, 4} (4 when 64x64 windows are present) and
- * persistent grids of {automatic, 128, 256, 384, 512, 768, 1024, resident
- * capacity} workgroups, timing each with HIP events on `stream`, and returns
- * *p with the fastest block_waves and workgroups in *best.  Neither changes
- * results.  Results are cached in-process per workload signature (sizes,
- * classes, precision, tiling); a cached signature returns at once.  Requires
- * the persistent schedule.  Errors as fse_extrapolate_batch. */
+/* Schedule autotuner: runs the given batch (outputs written to outs) under
+ * candidate schedules, timing each with HIP events on `stream`, and returns *p
+ * with the fastest schedule in *best:
+ *  - tiled modes with p->n_tiles == 0: first the tile count N of Algorithm 1
+ *    (Sec. III), from {16, 32, 64, 128, 256}, with the caller's stripe d and
+ *    the automatic grid (N, unlike the rest, changes results: the tile
+ *    framework's output depends on its tiles);
+ *  - then wave64s per block in {1, 2, 4}, or only p->block_waves when that is
+ *    not 0 (eight per workgroup when 64x64 windows are present), and
+ *    persistent grids of {automatic, 128, 256, 384,
+ *    512, 768, 1024, resident capacity} workgroups; neither changes results.
+ * The result is cached in-process per workload signature: sizes, classes,
+ * parameters, and the number of blocks and of dependency levels of the masks
+ * (from a first call), so masks of the same size but another structure are
+ * tuned anew; a cached signature returns after that first call.  Requires the
+ * persistent schedule.  Errors as fse_extrapolate_batch. */
 fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
                           fse_image_t* outs, void* stream, fse_params_t* best);
+
+/* The same search for callers that keep `streams` (2..8) consecutive calls in
+ * flight on as many streams: each candidate is timed over rounds of
+ * consecutive calls spread over `streams` streams of the tuner's own (the
+ * device runs several launches at once, where the best grid differs from a
+ * launch alone), by the host clock.  The first stream writes outs; the others
+ * write to temporary outputs the tuner allocates and frees.  Cached
+ * separately from fse_autotune. */
+fse_status_t fse_autotune_overlapped(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
+                                     const fse_params_t* p, fse_image_t* outs, int32_t streams,
+                                     fse_params_t* best);
 
 /* Free all cached device workspace (waits for the streams that use it).
  * Calls running on other threads finish first (each holds its workspace's

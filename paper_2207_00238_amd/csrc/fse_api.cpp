@@ -181,6 +181,7 @@ fse_status_t check_params(const fse_params_t* p, std::vector<ClassCfg>& cls) {
     if (p->schedule < FSE_SCHED_PERSISTENT || p->schedule > FSE_SCHED_PER_BLOCK) return FSE_ERR_INVALID_ARG;
     if (p->tiling != FSE_WHOLE && p->tiling != FSE_TILED && p->tiling != FSE_TILED_VERTICAL)
         return FSE_ERR_INVALID_ARG;
+    if (p->order != FSE_ORDER_RASTER && p->order != FSE_ORDER_OPTIMIZED) return FSE_ERR_INVALID_ARG;
     cls.clear();
     for (int c = 0; c < p->n_classes; ++c) {
         const fse_class_t& k = p->classes[c];
@@ -409,12 +410,22 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     if (ws.plan_scratch.size() < jobs.size()) ws.plan_scratch.resize(jobs.size());
     for (size_t j = 0; j < jobs.size(); ++j) jobs[j].plan = &ws.plans[j];
     std::vector<uint8_t> plan_ok(jobs.size(), 1);
+    // host threads for the optimised order's pair lists within one job: the
+    // jobs already run in parallel, so each gets its share of the threads
+    const int order_threads =
+        (int)std::max<size_t>(1, std::min<size_t>(16, std::max(1u, std::thread::hardware_concurrency())) / jobs.size());
     parallel_for(jobs.size(), [&](size_t j) {
         HostJob& J = jobs[j];
         const uint8_t* mk = ws.host_mask + moff[J.img] + (size_t)J.oy * images[J.img].width + J.ox;
         plan_ok[j] = plan_region(mk, images[J.img].width, J.W, J.H, cls, *J.plan, ws.plan_scratch[j]);
-        if (plan_ok[j] && p->schedule == FSE_SCHED_PERSISTENT)
+        if (plan_ok[j] && p->order == FSE_ORDER_OPTIMIZED) {
+            // blocks renumbered in the optimised order; levels (and the
+            // wavefront keys) over exactly the waits of that order
+            plan_priority_order(*J.plan, mk, images[J.img].width, cls, p->rho, p->recon_weight,
+                                ws.plan_scratch[j].order, order_threads);
+        } else if (plan_ok[j] && p->schedule == FSE_SCHED_PERSISTENT) {
             plan_levels(*J.plan, cls, reach, ws.plan_scratch[j].cell_level);
+        }
     });
     for (size_t j = 0; j < jobs.size(); ++j) {
         if (!plan_ok[j]) return FSE_ERR_INVALID_ARG;
@@ -618,7 +629,7 @@ fse_status_t prepare_batch(Workspace& ws, int n, const fse_image_t* images, cons
     }
     grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, ntk));
     if (p->schedule == FSE_SCHED_PER_BLOCK && ntk > 0) {
-        // plain path: one launch per block, raster order of each job
+        // plain path: one launch per block, in the processing order of each job
         std::vector<int32_t> raster(2 * ntk);
         size_t q = 0;
         for (size_t j = 0; j < jobs.size(); ++j)
@@ -840,70 +851,205 @@ fse_status_t fse_last_stats(fse_run_stats_t* st) {
     });
 }
 
+}  // extern "C"
+
+namespace fse {
+
+// ---------------------------------------------------------------------------
+// schedule autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, fse_params_t> g_tune_cache;
+
+// Device time of one call with parameters q (the second of two runs).
+fse_status_t time_call(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t& q,
+                       fse_image_t* outs, hipStream_t st, double& ms, fse_run_stats_t* rs_out = nullptr) {
+    fse_status_t s = FSE_OK;
+    for (int rep = 0; rep < 2; ++rep) {
+        if ((s = run_batch(n, images, masks, &q, outs, st)) != FSE_OK) return s;
+        fse_run_stats_t rs{};
+        if ((s = fse_last_stats(&rs)) != FSE_OK) return s;
+        if (rs.device_error) return FSE_ERR_DEVICE;
+        ms = rs.kernel_ms;
+        if (rs_out) *rs_out = rs;
+    }
+    return FSE_OK;
+}
+
+// Wall time of rounds of consecutive calls spread over the streams sts
+// (outputs: one set per stream), the device running several at once.
+fse_status_t time_overlapped(int n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t& q,
+                             const std::vector<std::vector<fse_image_t>>& outs, const std::vector<hipStream_t>& sts,
+                             double& ms) {
+    const int ns = (int)sts.size();
+    auto round = [&](int calls) -> fse_status_t {
+        for (int i = 0; i < calls; ++i) {
+            std::vector<fse_image_t> o = outs[i % ns];
+            fse_status_t s = run_batch(n, images, masks, &q, o.data(), sts[i % ns]);
+            if (s != FSE_OK) return s;
+        }
+        for (hipStream_t s : sts)
+            if (hipStreamSynchronize(s) != hipSuccess) return FSE_ERR_DEVICE;
+        return FSE_OK;
+    };
+    fse_status_t s = round(ns);  // every stream's workspace, untimed
+    if (s != FSE_OK) return s;
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((s = round(2 * ns)) != FSE_OK) return s;
+    ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / (2 * ns);
+    for (hipStream_t st : sts) {
+        int32_t err = 0;
+        if ((s = read_launch_error(st, &err)) != FSE_OK) return s;
+        if (err) return FSE_ERR_DEVICE;
+    }
+    return FSE_OK;
+}
+
+fse_status_t autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
+                      fse_image_t* outs, hipStream_t st, int streams, fse_params_t* best) {
+    if (!best || !p || streams < 1 || streams > 8) return FSE_ERR_INVALID_ARG;
+    // the tile count is searched when the caller leaves it to the tuner
+    const bool tune_tiles = p->tiling != FSE_WHOLE && p->n_tiles == 0;
+    fse_params_t q0 = *p;
+    q0.trace_sel = nullptr;
+    if (tune_tiles) q0.n_tiles = 64;
+    std::vector<ClassCfg> cls;
+    fse_status_t s = check_batch(n, images, masks, &q0, outs, cls);
+    if (s != FSE_OK) return s;
+    if (p->schedule != FSE_SCHED_PERSISTENT) return FSE_ERR_INVALID_ARG;
+    // a first call: its statistics (blocks and dependency levels of the
+    // masks) key the cache together with sizes, classes and parameters
+    double ms = 0;
+    fse_run_stats_t rs0{};
+    if ((s = time_call(n, images, masks, q0, outs, st, ms, &rs0)) != FSE_OK) return s;
+    std::string key = std::to_string(streams) + "/" + std::to_string(p->block_waves) + "/" +
+                      std::to_string(p->precision) + "/" +
+                      std::to_string(p->tiling) + "/" + std::to_string(p->n_tiles) + "/" +
+                      std::to_string(p->overlap) + "/" + std::to_string(p->align) + "/" + std::to_string(p->order) +
+                      "/" + std::to_string(rs0.n_blocks) + "/" + std::to_string(rs0.wavefront_keys);
+    for (auto& c : cls) key += "/" + std::to_string(c.B) + "," + std::to_string(c.b) + "," + std::to_string(c.K);
+    for (int i = 0; i < n; ++i) key += "/" + std::to_string(images[i].width) + "x" + std::to_string(images[i].height);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *best = *p;
+            best->n_tiles = it->second.n_tiles;
+            best->block_waves = it->second.block_waves;
+            best->workgroups = it->second.workgroups;
+            return FSE_OK;
+        }
+    }
+    bool wide = false;
+    for (auto& c : cls) wide |= (c.M == 64);
+    // consecutive calls in flight: streams of the tuner's own, with outputs of
+    // their own after the first (the caller's)
+    std::vector<hipStream_t> sts{st};
+    std::vector<std::vector<fse_image_t>> souts{std::vector<fse_image_t>(outs, outs + n)};
+    std::vector<void*> scratch_outs;
+    struct Cleanup {
+        std::vector<hipStream_t>& sts;
+        std::vector<void*>& bufs;
+        ~Cleanup() {
+            int dev = 0;
+            hipGetDevice(&dev);
+            for (size_t i = 1; i < sts.size(); ++i) {
+                hipStreamSynchronize(sts[i]);
+                release_workspace(dev, sts[i]);  // the stream's workspace, before the stream goes
+                hipStreamDestroy(sts[i]);
+            }
+            for (void* b : bufs) hipFree(b);
+        }
+    } cleanup{sts, scratch_outs};
+    for (int k = 1; k < streams; ++k) {
+        hipStream_t x = nullptr;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return FSE_ERR_DEVICE;
+        sts.push_back(x);
+        std::vector<fse_image_t> o(n);
+        for (int i = 0; i < n; ++i) {
+            void* b = nullptr;
+            const size_t bytes = (size_t)images[i].width * images[i].height * sizeof(float);
+            if (hipMalloc(&b, bytes) != hipSuccess) return FSE_ERR_OUT_OF_MEMORY;
+            scratch_outs.push_back(b);
+            o[i] = fse_image_t{(float*)b, images[i].width, images[i].height, images[i].width};
+        }
+        souts.push_back(o);
+    }
+    auto measure = [&](const fse_params_t& q, double& t) -> fse_status_t {
+        return streams == 1 ? time_call(n, images, masks, q, outs, st, t)
+                            : time_overlapped(n, images, masks, q, souts, sts, t);
+    };
+    fse_params_t cur = q0;
+    // 1. tiles (tiled modes, when asked): N of Sec. III with the automatic grid
+    if (tune_tiles) {
+        double best_ms = 1e30;
+        int best_n = 64;
+        for (int N : {16, 32, 64, 128, 256}) {
+            fse_params_t q = cur;
+            q.n_tiles = N;
+            q.workgroups = 0;
+            double t = 0;
+            if ((s = measure(q, t)) != FSE_OK) return s;
+            if (t < best_ms) {
+                best_ms = t;
+                best_n = N;
+            }
+        }
+        cur.n_tiles = best_n;
+    }
+    // 2. wave64s per block and persistent grid
+    const std::vector<int> waves = wide ? std::vector<int>{0}
+                                        : p->block_waves ? std::vector<int>{p->block_waves} : std::vector<int>{1, 2, 4};
+    double best_ms = 1e30;
+    int best_w = waves.back(), best_g = 0;
+    for (int w : waves) {
+        const int cap = persistent_grid(wide ? kWideWaves : w, p->precision, wide);
+        std::vector<int> grids{0};
+        for (int g : {128, 256, 384, 512, 768, 1024})
+            if (g < cap) grids.push_back(g);
+        grids.push_back(cap);
+        for (int g : grids) {
+            fse_params_t q = cur;
+            q.block_waves = w;
+            q.workgroups = g;
+            double t = 0;
+            if ((s = measure(q, t)) != FSE_OK) return s;
+            if (t < best_ms) {
+                best_ms = t;
+                best_w = w;
+                best_g = g;
+            }
+        }
+    }
+    *best = *p;
+    best->n_tiles = cur.n_tiles;
+    best->block_waves = best_w;
+    best->workgroups = best_g;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = *best;
+    return FSE_OK;
+}
+
+}  // namespace
+}  // namespace fse
+
+extern "C" {
+
 fse_status_t fse_autotune(int32_t n, const fse_image_t* images, const fse_mask_t* masks, const fse_params_t* p,
                           fse_image_t* outs, void* stream, fse_params_t* best) {
     return abi_guard([&]() -> fse_status_t {
-        using namespace fse;
-        if (!best) return FSE_ERR_INVALID_ARG;
-        std::vector<ClassCfg> cls;
-        fse_status_t s = check_batch(n, images, masks, p, outs, cls);
-        if (s != FSE_OK) return s;
-        if (p->schedule != FSE_SCHED_PERSISTENT) return FSE_ERR_INVALID_ARG;
-        // workload signature: sizes, classes, precision, tiling
-        std::string key = std::to_string(p->precision) + "/" + std::to_string(p->tiling) + "/" +
-                          std::to_string(p->n_tiles) + "/" + std::to_string(p->overlap);
-        for (auto& c : cls) key += "/" + std::to_string(c.B) + "," + std::to_string(c.b) + "," + std::to_string(c.K);
-        for (int i = 0; i < n; ++i) key += "/" + std::to_string(images[i].width) + "x" + std::to_string(images[i].height);
-        static std::mutex cache_mu;
-        static std::map<std::string, std::pair<int, int>> cache;
-        *best = *p;
-        {
-            std::lock_guard<std::mutex> lk(cache_mu);
-            auto it = cache.find(key);
-            if (it != cache.end()) {
-                best->block_waves = it->second.first;
-                best->workgroups = it->second.second;
-                return FSE_OK;
-            }
-        }
-        bool wide = false;
-        for (auto& c : cls) wide |= (c.M == 64);
-        // launches with 64 x 64 windows have a fixed workgroup shape (block_waves 0)
-        std::vector<int> waves = wide ? std::vector<int>{0} : std::vector<int>{2, 4};
-        double best_ms = 1e30;
-        int best_w = waves.front(), best_g = 0;
-        hipStream_t st = (hipStream_t)stream;
-        for (int w : waves) {
-            const int cap = persistent_grid(wide ? kWideWaves : w, p->precision, wide);
-            std::vector<int> grids{0};
-            for (int g : {128, 256, 384, 512, 768, 1024})
-                if (g < cap) grids.push_back(g);
-            grids.push_back(cap);
-            for (int g : grids) {
-                fse_params_t q = *p;
-                q.block_waves = w;
-                q.workgroups = g;
-                q.trace_sel = nullptr;
-                double ms = 0;
-                for (int rep = 0; rep < 2; ++rep) {
-                    if ((s = run_batch(n, images, masks, &q, outs, st)) != FSE_OK) return s;
-                    fse_run_stats_t rs{};
-                    if ((s = fse_last_stats(&rs)) != FSE_OK) return s;
-                    if (rs.device_error) return FSE_ERR_DEVICE;
-                    ms = rs.kernel_ms;
-                }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_w = w;
-                    best_g = g;
-                }
-            }
-        }
-        best->block_waves = best_w;
-        best->workgroups = best_g;
-        std::lock_guard<std::mutex> lk(cache_mu);
-        cache[key] = {best_w, best_g};
-        return FSE_OK;
+        return fse::autotune(n, images, masks, p, outs, (hipStream_t)stream, 1, best);
+    });
+}
+
+fse_status_t fse_autotune_overlapped(int32_t n, const fse_image_t* images, const fse_mask_t* masks,
+                                     const fse_params_t* p, fse_image_t* outs, int32_t streams,
+                                     fse_params_t* best) {
+    return abi_guard([&]() -> fse_status_t {
+        if (streams < 2) return FSE_ERR_INVALID_ARG;
+        return fse::autotune(n, images, masks, p, outs, nullptr, streams, best);
     });
 }
 

@@ -8,6 +8,8 @@
 #include "fse_plan.h"
 
 #include <algorithm>
+#include <cmath>
+#include <thread>
 #if defined(__SSE2__)
 #include <emmintrin.h>
 #endif
@@ -262,41 +264,366 @@ void plan_levels(RegionPlan& P, const std::vector<ClassCfg>& cls, int reach, std
     }
 }
 
+// ---------------------------------------------------------------------------
+// optimised processing order
+// ---------------------------------------------------------------------------
+namespace {
+
+typedef unsigned __int128 u128;
+constexpr int kMaxPlanClasses = 8;
+
+// fn(t, i0, i1) for nt contiguous chunks [i0, i1) of [0, n), chunk t on a
+// thread of its own (the calling thread takes the last)
+template <class F>
+void run_chunks(int n, int nt, F&& fn) {
+    std::vector<std::thread> th;
+    th.reserve(nt > 1 ? nt - 1 : 0);
+    for (int t = 0; t + 1 < nt; ++t)
+        th.emplace_back([&, t] { fn(t, (int)((int64_t)n * t / nt), (int)((int64_t)n * (t + 1) / nt)); });
+    fn(nt - 1, (int)((int64_t)n * (nt - 1) / nt), n);
+    for (auto& x : th) x.join();
+}
+
+// Indexed binary max-heap of blocks: a block ranks higher when its share of
+// usable weight is larger (share / full of its class, compared exactly by
+// cross-multiplication), then when its raster index is smaller.  Each entry
+// carries its block's share, so comparisons read the heap array only.
+struct ShareHeap {
+    const int64_t* full;  // per class
+    HeapEntry* heap;
+    int32_t* pos;         // entry of every block, -1 once popped
+    int n = 0;
+    bool one_full = false;  // every class has the same full-window weight: compare shares directly
+    bool above(const HeapEntry& a, const HeapEntry& b) const {
+        if (one_full) return a.share > b.share || (a.share == b.share && a.id < b.id);
+        const u128 l = (u128)(uint64_t)a.share * (uint64_t)full[b.cls];
+        const u128 r = (u128)(uint64_t)b.share * (uint64_t)full[a.cls];
+        return l > r || (l == r && a.id < b.id);
+    }
+    void place(int k, const HeapEntry& e) {
+        heap[k] = e;
+        pos[e.id] = k;
+    }
+    void up(int k) {
+        const HeapEntry e = heap[k];
+        while (k > 0) {
+            const int parent = (k - 1) >> 1;
+            if (!above(e, heap[parent])) break;
+            place(k, heap[parent]);
+            k = parent;
+        }
+        place(k, e);
+    }
+    void down(int k) {
+        const HeapEntry e = heap[k];
+        for (;;) {
+            int c = 2 * k + 1;
+            if (c >= n) break;
+            if (c + 1 < n && above(heap[c + 1], heap[c])) ++c;
+            if (!above(heap[c], e)) break;
+            place(k, heap[c]);
+            k = c;
+        }
+        place(k, e);
+    }
+    // block i's share grows by d
+    void raise(int i, int64_t d) {
+        heap[pos[i]].share += d;
+        up(pos[i]);
+    }
+    int pop() {
+        const int top = heap[0].id;
+        pos[top] = -1;
+        if (--n > 0) {
+            place(0, heap[n]);
+            down(0);
+        }
+        return top;
+    }
+};
+
+}  // namespace
+
+void plan_priority_order(RegionPlan& P, const uint8_t* mask, int64_t pitch, const std::vector<ClassCfg>& cls,
+                         double rho, double delta, OrderScratch& S, int threads) {
+    const int n = (int)(P.desc.size() / 4);
+    const int nc = (int)cls.size();
+    if (n <= 1 || nc > kMaxPlanClasses) {
+        P.level.assign(n, 0);
+        P.key = P.level;
+        return;
+    }
+    const int Bmin = cls.back().B;
+    // integer weights per class: known and reconstructed, each with its 2-D
+    // prefix sum (sums over rectangles of the window in O(1))
+    std::vector<size_t> t_known(nc), t_rec(nc), t_pk(nc), t_pr(nc);
+    std::vector<int64_t> full(nc);
+    size_t tot = 0;
+    for (int c = 0; c < nc; ++c) {
+        const size_t MM = (size_t)cls[c].M * cls[c].M, M1 = (size_t)(cls[c].M + 1) * (cls[c].M + 1);
+        t_known[c] = tot;
+        t_rec[c] = tot + MM;
+        t_pk[c] = tot + 2 * MM;
+        t_pr[c] = tot + 2 * MM + M1;
+        tot += 2 * MM + 2 * M1;
+    }
+    S.qtab.assign(tot, 0);
+    for (int c = 0; c < nc; ++c) {
+        const int M = cls[c].M;
+        int64_t* qk = &S.qtab[t_known[c]];
+        int64_t* qr = &S.qtab[t_rec[c]];
+        const double mid = 0.5 * (M - 1);
+        for (int m = 0; m < M; ++m)
+            for (int k = 0; k < M; ++k) {
+                const double dy = m - mid, dx = k - mid;
+                const double w = std::pow(rho, std::sqrt(dy * dy + dx * dx));
+                qk[m * M + k] = std::llround(std::ldexp(w, 30));
+                qr[m * M + k] = std::llround(std::ldexp(delta * w, 30));
+            }
+        for (int t = 0; t < 2; ++t) {
+            const int64_t* q = t ? qr : qk;
+            int64_t* pre = &S.qtab[t ? t_pr[c] : t_pk[c]];
+            for (int m = 0; m < M; ++m)
+                for (int k = 0; k < M; ++k)
+                    pre[(m + 1) * (M + 1) + k + 1] =
+                        q[m * M + k] + pre[m * (M + 1) + k + 1] + pre[(m + 1) * (M + 1) + k] - pre[m * (M + 1) + k];
+        }
+        full[c] = S.qtab[t_pk[c] + (size_t)M * (M + 1) + M];
+    }
+    // sum of a prefix-summed table over rows [m0, m1) and columns [k0, k1)
+    auto rect = [](const int64_t* pre, int M, int m0, int m1, int k0, int k1) -> int64_t {
+        if (m1 <= m0 || k1 <= k0) return 0;
+        return pre[m1 * (M + 1) + k1] - pre[m0 * (M + 1) + k1] - pre[m1 * (M + 1) + k0] + pre[m0 * (M + 1) + k0];
+    };
+    // lost pixels of every block, grouped by block
+    S.lost_off.resize(n + 1);
+    S.lost_yx.clear();
+    for (int j = 0; j < n; ++j) {
+        S.lost_off[j] = (int32_t)(S.lost_yx.size() / 2);
+        const int32_t* lb = &P.lbox[4 * j];
+        for (int y = lb[0]; y < lb[2]; ++y)
+            for (int x = lb[1]; x < lb[3]; ++x)
+                if (mask[(int64_t)y * pitch + x] && P.owner[(size_t)(y / Bmin) * P.fw + x / Bmin] == j) {
+                    S.lost_yx.push_back(y);
+                    S.lost_yx.push_back(x);
+                }
+    }
+    S.lost_off[n] = (int32_t)(S.lost_yx.size() / 2);
+    // every block i whose window meets the lost pixels of block j:
+    // fn(i, sum over those pixels of table t of i's class, at their window
+    // positions); table 0 = known weights, 1 = reconstructed weights
+    int Rmax = 0;
+    for (auto& c : cls) Rmax = std::max(Rmax, c.B + c.b);
+    // raw views of the tables the scans read
+    const int32_t* desc = P.desc.data();
+    const int32_t* lbox = P.lbox.data();
+    const int32_t* loff = S.lost_off.data();
+    const int32_t* lyx = S.lost_yx.data();
+    const int64_t* qtab = S.qtab.data();
+    const int fh = P.fh;
+    int cb[kMaxPlanClasses], cM[kMaxPlanClasses];
+    size_t tk[kMaxPlanClasses], tr[kMaxPlanClasses], pk[kMaxPlanClasses], pr[kMaxPlanClasses];
+    for (int c = 0; c < nc; ++c) {
+        cb[c] = cls[c].b;
+        cM[c] = cls[c].M;
+        tk[c] = t_known[c];
+        tr[c] = t_rec[c];
+        pk[c] = t_pk[c];
+        pr[c] = t_pr[c];
+    }
+    // blocks by corner cell: the blocks are in raster order of their corner
+    // cells, so first[fy][fx] -- the first block whose corner is in row fy at
+    // column >= fx (fx = 0 .. fw) -- bounds every row's run of blocks
+    const int fw1 = P.fw + 1;
+    S.tmp.resize((size_t)fw1 * fh + 1);
+    int32_t* first = S.tmp.data();
+    {
+        int i = 0;
+        for (int fy = 0; fy < fh; ++fy)
+            for (int fx = 0; fx <= P.fw; ++fx) {
+                while (i < n && (desc[4 * i] / Bmin < fy || (desc[4 * i] / Bmin == fy && desc[4 * i + 1] / Bmin < fx)))
+                    ++i;
+                first[(size_t)fy * fw1 + fx] = i;
+            }
+        first[(size_t)fw1 * fh] = n;
+    }
+    int bmax = 0;
+    for (auto& c : cls) bmax = std::max(bmax, c.b);
+    // every block i whose window meets the lost box of block j: its corner
+    // lies within rows (lb0 - B_i - b_i, lb2 + b_i) and the same columns;
+    // fn(i, sum of table t of i's class over j's lost pixels in i's window)
+    // with t = 0 the known weights, 1 the reconstructed ones
+    auto pixel_sum = [&](int j, int c, int wy, int wx, int table) -> int64_t {
+        const int32_t* lb = &lbox[4 * j];
+        const int M = cM[c];
+        if ((int64_t)(loff[j + 1] - loff[j]) == (int64_t)(lb[2] - lb[0]) * (lb[3] - lb[1]))
+            // every pixel of the box is lost: one rectangle of the table
+            return rect(qtab + (table ? pr[c] : pk[c]), M, std::max(0, lb[0] - wy), std::min(M, lb[2] - wy),
+                        std::max(0, lb[1] - wx), std::min(M, lb[3] - wx));
+        const int64_t* q = qtab + (table ? tr[c] : tk[c]);
+        int64_t sum = 0;
+        for (int k = loff[j]; k < loff[j + 1]; ++k) {
+            const int m = lyx[2 * k] - wy, x = lyx[2 * k + 1] - wx;
+            if (m >= 0 && m < M && x >= 0 && x < M) sum += q[m * M + x];
+        }
+        return sum;
+    };
+    auto for_windows_meeting = [&](int j, auto&& fn) {
+        const int32_t* lb = &lbox[4 * j];
+        const int fy0 = std::max(0, (lb[0] - Rmax + 1) / Bmin), fy1 = std::min(fh - 1, (lb[2] + bmax - 1) / Bmin);
+        const int fx0 = std::max(0, (lb[1] - Rmax + 1) / Bmin), fx1 = std::min(P.fw - 1, (lb[3] + bmax - 1) / Bmin);
+        for (int fy = fy0; fy <= fy1; ++fy) {
+            const int i1 = first[(size_t)fy * fw1 + fx1 + 1];
+            for (int i = first[(size_t)fy * fw1 + fx0]; i < i1; ++i) {
+                const int32_t* di = &desc[4 * i];
+                const int c = di[2], M = cM[c];
+                const int wy = di[0] - cb[c], wx = di[1] - cb[c];
+                if (meet(lb[0], lb[1], lb[2], lb[3], wy, wx, wy + M, wx + M)) fn(i, c, wy, wx);
+            }
+        }
+    };
+    // the pairs, by j: every i whose window meets j's lost box, with the sum
+    // of i's reconstructed weights over j's lost pixels (what i's share gains
+    // when j is processed).  Counted, then filled in place, by chunks of
+    // blocks on threads of their own.
+    const int nth = std::max(1, std::min(threads, n / 256 + 1));
+    S.adj_off.assign(n + 1, 0);
+    run_chunks(n, nth, [&](int, int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            int cnt = 0;
+            for_windows_meeting(j, [&](int, int, int, int) { ++cnt; });
+            S.adj_off[j + 1] = cnt;
+        }
+    });
+    for (int j = 0; j < n; ++j) S.adj_off[j + 1] += S.adj_off[j];
+    S.adj_i.resize(S.adj_off[n]);
+    S.adj_s.resize(S.adj_off[n]);
+    run_chunks(n, nth, [&](int, int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            int e = S.adj_off[j];
+            for_windows_meeting(j, [&](int i, int c, int wy, int wx) {
+                S.adj_i[e] = i;
+                S.adj_s[e] = pixel_sum(j, c, wy, wx, 1);
+                ++e;
+            });
+        }
+    });
+    // initial shares, per block i on the threads: known weights of its window
+    // inside the region, minus those of the lost pixels in it (the lost boxes
+    // that meet the window: corners within rows (wy - Bmax, wy + M))
+    int Bmax = 0;
+    for (auto& c : cls) Bmax = std::max(Bmax, c.B);
+    S.share.resize(n);
+    run_chunks(n, nth, [&](int, int i0, int i1) {
+        for (int i = i0; i < i1; ++i) {
+            const int32_t* di = &desc[4 * i];
+            const int c = di[2], M = cM[c];
+            const int wy = di[0] - cb[c], wx = di[1] - cb[c];
+            int64_t sh = rect(qtab + pk[c], M, std::max(0, -wy), std::min(M, P.H - wy), std::max(0, -wx),
+                              std::min(M, P.W - wx));
+            const int fy0 = std::max(0, (wy - Bmax + 1) / Bmin), fy1 = std::min(fh - 1, (wy + M - 1) / Bmin);
+            const int fx0 = std::max(0, (wx - Bmax + 1) / Bmin), fx1 = std::min(P.fw - 1, (wx + M - 1) / Bmin);
+            for (int fy = fy0; fy <= fy1; ++fy) {
+                const int j1 = first[(size_t)fy * fw1 + fx1 + 1];
+                for (int j = first[(size_t)fy * fw1 + fx0]; j < j1; ++j) {
+                    const int32_t* lb = &lbox[4 * j];
+                    if (meet(lb[0], lb[1], lb[2], lb[3], wy, wx, wy + M, wx + M)) sh -= pixel_sum(j, c, wy, wx, 0);
+                }
+            }
+            S.share[i] = sh;
+        }
+    });
+    // greedy: the best remaining block; its lost pixels turn reconstructed.
+    // The dependency levels of that order come along, over exactly the waits
+    // of the block kernel: two blocks interact when either one's lost box
+    // meets the other's window -- each such pair is some (j, i in j's list).
+    // When j is processed it takes its level from the listed blocks processed
+    // before it (and from the raises it received from earlier blocks whose
+    // lists hold it), then raises the listed blocks still to come.
+    S.heap.resize(n);
+    S.pos.resize(n);
+    ShareHeap hp{full.data(), S.heap.data(), S.pos.data(), n};
+    hp.one_full = std::all_of(full.begin(), full.end(), [&](int64_t f) { return f == full[0]; });
+    for (int i = 0; i < n; ++i) hp.place(i, HeapEntry{S.share[i], i, desc[4 * i + 2]});
+    for (int k = n / 2 - 1; k >= 0; --k) hp.down(k);
+    S.perm.resize(n);
+    S.level.assign(n, 0);
+    const int32_t* aoff = S.adj_off.data();
+    const int32_t* ai = S.adj_i.data();
+    const int64_t* as = S.adj_s.data();
+    int32_t* pos = S.pos.data();
+    int32_t* lev = S.level.data();
+    for (int k = 0; k < n; ++k) {
+        const int j = hp.pop();  // pos[j] = -1 from here on
+        S.perm[k] = j;
+        int lv = lev[j];
+        for (int e = aoff[j]; e < aoff[j + 1]; ++e) {
+            const int i = ai[e];  // (j's own window meets its lost box: j is in its list)
+            if (i != j && pos[i] < 0 && lev[i] + 1 > lv) lv = lev[i] + 1;
+        }
+        lev[j] = lv;
+        for (int e = aoff[j]; e < aoff[j + 1]; ++e) {
+            const int i = ai[e];
+            if (pos[i] < 0) continue;  // processed already (or j itself)
+            if (lev[i] < lv + 1) lev[i] = lv + 1;
+            if (as[e] != 0) hp.raise(i, as[e]);
+        }
+    }
+    S.rank.resize(n);
+    for (int k = 0; k < n; ++k) S.rank[S.perm[k]] = k;
+    // renumber: block k of the plan is the k-th processed
+    for (auto& o : P.owner)
+        if (o >= 0) o = S.rank[o];
+    std::vector<int32_t> d2(4 * (size_t)n), l2(4 * (size_t)n);
+    P.level.resize(n);
+    for (int k = 0; k < n; ++k) {
+        for (int q = 0; q < 4; ++q) {
+            d2[4 * k + q] = P.desc[4 * (size_t)S.perm[k] + q];
+            l2[4 * k + q] = P.lbox[4 * (size_t)S.perm[k] + q];
+        }
+        P.level[k] = S.level[S.perm[k]];
+    }
+    P.desc.swap(d2);
+    P.lbox.swap(l2);
+    P.key = P.level;
+}
+
+// Tiles of one row holding n tiles of a length L: eq. (5) gives the first
+// L mod n tiles the width ceil(L / n) and the rest floor(L / n), so tile j
+// (0-based) starts at j floor(L / n) + min(j, L mod n).
+static inline int64_t split_start(int64_t L, int64_t n, int64_t j) { return j * (L / n) + std::min(j, L % n); }
+
 bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
     xywh.clear();
     if (W < 1 || H < 1 || N < 1) return false;
+    // portrait images are tiled as their transpose (landscape is assumed)
     const bool portrait = W < H;
     const int64_t Wl = portrait ? H : W, Hl = portrait ? W : H;
-    // eq. (2): n_R = max(1, round(sqrt(N / r))) with r = Wl / Hl (eq. (1)).
-    // round(sqrt(q)) = k  iff  (2k - 1)^2 <= 4q < (2k + 1)^2,  4q = 4 N Hl / Wl
+    // eqs. (1)-(2): rows nR = max(1, round(sqrt(N / r))), r = Wl / Hl, with
+    // round(sqrt(q)) = k  iff  (2k - 1)^2 <= 4q < (2k + 1)^2 and 4q = 4 N Hl / Wl
     int64_t k = 0;
     while ((2 * k + 1) * (2 * k + 1) * Wl <= 4 * (int64_t)N * Hl) ++k;
     const int64_t nR = std::max<int64_t>(1, k);
-    int64_t yT = 0;
-    std::vector<int32_t> land;
-    for (int64_t i = 1; i <= nR; ++i) {
-        // eq. (3): tiles in this row
-        const int64_t nC = (i <= N % nR) ? (N + nR - 1) / nR : N / nR;
-        // eq. (4): row height; the last row takes what is left
-        int64_t hT = (Hl * nC) / N + ((Hl * nC) % N) / nR;
-        if (i == nR) hT = Hl - yT;
-        // for large N eq. (4) overshoots the image height; rows are clipped at
-        // the bottom edge and rows past it stay empty
-        hT = std::max<int64_t>(0, std::min<int64_t>(hT, Hl - yT));
-        int64_t xT = 0;
-        for (int64_t j = 1; j <= nC; ++j) {
-            // eq. (5): tile width
-            const int64_t wT = (j <= Wl % nC) ? (Wl + nC - 1) / nC : Wl / nC;
-            land.insert(land.end(), {(int32_t)xT, (int32_t)yT, (int32_t)wT, (int32_t)hT});
-            xT += wT;
+    // eq. (3): the first N mod nR rows hold ceil(N / nR) tiles, the others
+    // floor(N / nR); eq. (4) then gives one height per kind of row
+    const int64_t n_hi = (N + nR - 1) / nR, n_lo = N / nR, rows_hi = N % nR;
+    auto height = [&](int64_t nC) { return (Hl * nC) / N + ((Hl * nC) % N) / nR; };
+    const int64_t h_hi = height(n_hi), h_lo = height(n_lo);
+    // row i (0-based) starts below i rows: min(i, rows_hi) of height h_hi and
+    // the rest of height h_lo; the last row reaches the bottom edge.  For
+    // large N eq. (4) can pass the bottom edge: rows are clipped there, and
+    // rows below it are empty.
+    auto row_top = [&](int64_t i) { return std::min(Hl, std::min(i, rows_hi) * h_hi + std::max<int64_t>(0, i - rows_hi) * h_lo); };
+    for (int64_t i = 0; i < nR; ++i) {
+        const int64_t y0 = row_top(i), y1 = (i + 1 == nR) ? Hl : row_top(i + 1);
+        const int64_t nC = i < rows_hi ? n_hi : n_lo;
+        for (int64_t j = 0; j < nC; ++j) {
+            const int64_t x0 = split_start(Wl, nC, j), x1 = split_start(Wl, nC, j + 1);
+            if (!portrait)
+                xywh.insert(xywh.end(), {(int32_t)x0, (int32_t)y0, (int32_t)(x1 - x0), (int32_t)(y1 - y0)});
+            else
+                xywh.insert(xywh.end(), {(int32_t)y0, (int32_t)x0, (int32_t)(y1 - y0), (int32_t)(x1 - x0)});
         }
-        yT += hT;
-    }
-    if (!portrait) {
-        xywh = land;
-    } else {
-        for (size_t t = 0; t < land.size(); t += 4)
-            xywh.insert(xywh.end(), {land[t + 1], land[t], land[t + 3], land[t + 2]});
     }
     return true;
 }
@@ -304,11 +631,9 @@ bool compact_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
 bool vertical_tiling(int W, int H, int N, std::vector<int32_t>& xywh) {
     xywh.clear();
     if (W < 1 || H < 1 || N < 1) return false;
-    int64_t xT = 0;
-    for (int64_t j = 1; j <= N; ++j) {
-        const int64_t wT = (j <= W % N) ? (W + N - 1) / N : W / N;
-        xywh.insert(xywh.end(), {(int32_t)xT, 0, (int32_t)wT, (int32_t)H});
-        xT += wT;
+    for (int64_t j = 0; j < N; ++j) {
+        const int64_t x0 = split_start(W, N, j), x1 = split_start(W, N, j + 1);
+        xywh.insert(xywh.end(), {(int32_t)x0, 0, (int32_t)(x1 - x0), (int32_t)H});
     }
     return true;
 }

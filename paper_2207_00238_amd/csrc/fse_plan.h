@@ -8,6 +8,12 @@
 
 namespace fse {
 
+// entry of the optimised order's heap: a block and its share (fse_plan.cpp)
+struct HeapEntry {
+    int64_t share;
+    int32_t id, cls;
+};
+
 struct ClassCfg {
     int B, b, K, M;
 };
@@ -24,6 +30,23 @@ struct RegionPlan {
     int64_t lost_pixels = 0;
 };
 
+// Working storage of plan_priority_order, kept between calls.
+struct OrderScratch {
+    std::vector<int64_t> share;     // per block: usable window weight (exact integer)
+    std::vector<HeapEntry> heap;  // max-heap of the blocks not yet processed
+    std::vector<int32_t> pos;     // heap entry of every block
+    std::vector<int32_t> lost_off;  // per block: start of its lost pixels in lost_yx
+    std::vector<int32_t> lost_yx;   // lost pixels, (y, x) pairs, grouped by block
+    std::vector<int32_t> adj_off;   // per block j: start of its pairs
+    std::vector<int32_t> adj_i;     // the blocks whose windows meet j's lost pixels
+    std::vector<int64_t> adj_s;     // and what each one's share gains when j is processed
+    std::vector<int32_t> perm;      // processing order (raster indices)
+    std::vector<int32_t> rank;      // position of every raster block in that order
+    std::vector<int32_t> level;     // dependency level per raster block
+    std::vector<int32_t> tmp;       // first block per corner cell
+    std::vector<int64_t> qtab;      // per class: known weights, reconstructed weights, prefix sums
+};
+
 // Working storage of plan_region, kept by the caller between calls so that
 // repeated planning reuses its memory.
 struct PlanScratch {
@@ -32,6 +55,7 @@ struct PlanScratch {
     std::vector<int32_t> corner;  // per fine cell: block id of a corner cell
     std::vector<uint64_t> bits;   // Bmin mask rows as bit sets
     std::vector<int32_t> cell_level;  // plan_levels: level of each cell's owner
+    OrderScratch order;               // plan_priority_order
 };
 
 // Block geometry shared by the planner and the kernels: the largest class
@@ -47,6 +71,25 @@ bool plan_region(const uint8_t* mask, int64_t pitch, int W, int H, const std::ve
 // by level keeps ready blocks ahead of blocks deep in a chain.  cell_level:
 // scratch, resized here.
 void plan_levels(RegionPlan& P, const std::vector<ClassCfg>& cls, int reach, std::vector<int32_t>& stamp);
+
+
+// Optimised processing order (Sec. II: large lost areas close from their
+// margins towards their centre).  Each step takes the block, among those not
+// yet processed, whose support window offers the largest share of usable
+// weight -- its sum of R7 weights under the current statuses (rho^dist known,
+// delta rho^dist reconstructed, 0 lost or off the region) over that sum for
+// a fully known window of its class -- with ties to the raster-earlier block.
+// Weights are the integers round(2^30 rho^dist) and round(2^30 delta
+// rho^dist), so the shares are exact.  Renumbers the blocks of P in that
+// order (desc, lbox, owner), so that a smaller block index still means
+// "processed earlier" everywhere, and sets P.level (and P.key = P.level, the
+// wavefront schedule's keys): 1 + the largest level of the earlier blocks
+// that interact with the block -- exactly the blocks the kernel waits for.
+// mask is the region view used to plan P.
+// The pair lists and the initial shares are built on up to `threads` host
+// threads; the greedy choice itself is sequential.
+void plan_priority_order(RegionPlan& P, const uint8_t* mask, int64_t pitch, const std::vector<ClassCfg>& cls,
+                         double rho, double delta, OrderScratch& S, int threads);
 
 // Key slope: a block can only interact with blocks whose corner lies at most
 // D fine cells to its right in an earlier row, so key = cx + (D + 1) cy

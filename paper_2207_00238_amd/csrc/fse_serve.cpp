@@ -3,8 +3,9 @@
 // A server owns `max_slots` HIP streams.  Submitted requests wait in a FIFO
 // queue.  A scheduler thread repeatedly takes the requests that fit the HBM
 // budget (estimated per request from its size), groups those with identical
-// parameters, and launches each group as one batched persistent extrapolation
-// on a free stream slot.  Launches on different slots run concurrently on the
+// parameters, and hands each group to a free stream slot, whose own thread
+// plans it on the host and launches it as one batched persistent
+// extrapolation (so the planning of several groups runs at once).  Launches on different slots run concurrently on the
 // device, so requests that arrive while earlier ones are on the GPU join the
 // next launch and overlap with them.  A launch's completion (an event on its
 // stream) releases its budget and marks its requests done -- or failed, when
@@ -49,12 +50,21 @@ struct Request {
     fse_status_t status = FSE_OK;
 };
 
+// A slot: a stream, and a thread that plans and launches the groups the
+// scheduler hands to it, so that the host planning of one group overlaps the
+// admission and planning of others.
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done_ev = nullptr;
     std::vector<std::shared_ptr<Request>> reqs;
     int64_t bytes = 0;
-    bool busy = false;
+    bool busy = false;      // holds a group (being planned, or launched)
+    bool assigned = false;  // a group waits for the slot's thread
+    bool launched = false;  // the group's launch is enqueued and done_ev recorded
+    fse_params_t params{};
+    std::vector<fse_image_t> images, outs;
+    std::vector<fse_mask_t> masks;
+    std::thread thread;
 };
 
 }  // namespace fse
@@ -70,6 +80,8 @@ struct fse_server {
     int64_t bytes_in_use = 0;
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool stop_slots = false;
+    std::condition_variable slot_cv;  // wakes the slot threads
     std::thread worker;
 };
 
@@ -92,7 +104,7 @@ static int64_t request_bytes(const fse_image_t& im, const fse_params_t& p) {
 static bool same_params(const fse_params_t& a, const fse_params_t& b) {
     if (a.n_classes != b.n_classes || a.rho != b.rho || a.gamma != b.gamma || a.recon_weight != b.recon_weight ||
         a.precision != b.precision || a.schedule != b.schedule || a.tiling != b.tiling || a.workgroups != b.workgroups ||
-        a.block_waves != b.block_waves)
+        a.block_waves != b.block_waves || a.order != b.order)
         return false;
     for (int c = 0; c < a.n_classes; ++c)
         if (a.classes[c].block != b.classes[c].block || a.classes[c].border != b.classes[c].border ||
@@ -131,6 +143,10 @@ static bool schedule_once(fse_server* S, std::unique_lock<std::mutex>& lk) {
     bool any_running = false;
     for (auto& sl : S->slots) {
         if (!sl.busy) continue;
+        if (!sl.launched) {  // still being planned by its thread
+            any_running = true;
+            continue;
+        }
         const hipError_t q = hipEventQuery(sl.done_ev);
         if (q == hipErrorNotReady) {
             any_running = true;
@@ -168,6 +184,12 @@ static bool schedule_once(fse_server* S, std::unique_lock<std::mutex>& lk) {
             mks.push_back(r->mask);
         }
         if (!take.empty()) {
+            Slot& sl = S->slots[free_slot];
+            // the group's arguments go to the slot (reserved before any state
+            // changes, so that an allocation failure leaves the queue intact)
+            sl.images.reserve(ims.size());
+            sl.outs.reserve(outs.size());
+            sl.masks.reserve(mks.size());
             // the picked requests leave the queue (in queue order; no allocation)
             size_t k = 0;
             S->queue.erase(std::remove_if(S->queue.begin(), S->queue.end(),
@@ -179,33 +201,59 @@ static bool schedule_once(fse_server* S, std::unique_lock<std::mutex>& lk) {
                                               return false;
                                           }),
                            S->queue.end());
-            Slot& sl = S->slots[free_slot];
             sl.busy = true;
+            sl.launched = false;
+            sl.assigned = true;
             sl.reqs.swap(take);
             sl.bytes = bytes;
+            sl.images.swap(ims);
+            sl.outs.swap(outs);
+            sl.masks.swap(mks);
+            sl.params = p0;
+            sl.params.trace_sel = nullptr;
             S->bytes_in_use += bytes;
             const double t = steady_ms();
             for (auto& r : sl.reqs) {
                 r->t_admit = t;
                 r->state = 1;
             }
-            fse_params_t p = p0;
-            p.trace_sel = nullptr;
-            lk.unlock();
-            fse_status_t s = abi_guard(
-                [&] { return run_batch((int)ims.size(), ims.data(), mks.data(), &p, outs.data(), sl.stream); });
-            fse_run_stats_t st{};
-            fse_last_stats_nowait(&st);
-            if (s == FSE_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) s = FSE_ERR_DEVICE;
-            lk.lock();
-            const int64_t per = st.n_blocks / (int64_t)sl.reqs.size();
-            for (auto& r : sl.reqs) r->n_blocks = per;
-            if (s != FSE_OK) finish_slot(S, sl, s);
+            S->slot_cv.notify_all();
             return true;  // try to fill another slot at once
         }
     }
     S->cv.wait_for(lk, std::chrono::microseconds(any_running ? 100 : 2000));
     return true;
+}
+
+// A slot's thread: plans and launches each group handed to the slot on the
+// slot's stream (run_batch), records the completion event, and hands the
+// launch back to the scheduler.
+static void slot_thread(fse_server* S, size_t idx) {
+    (void)hipSetDevice(S->cfg.device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        Slot& sl = S->slots[idx];
+        S->slot_cv.wait(lk, [&] { return sl.assigned || S->stop_slots; });
+        if (!sl.assigned) break;
+        sl.assigned = false;
+        const int n = (int)sl.images.size();
+        lk.unlock();
+        // the slot's group is not touched by anyone else until it is launched
+        fse_status_t s = abi_guard([&] {
+            return run_batch(n, sl.images.data(), sl.masks.data(), &sl.params, sl.outs.data(), sl.stream);
+        });
+        fse_run_stats_t st{};
+        fse_last_stats_nowait(&st);
+        if (s == FSE_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) s = FSE_ERR_DEVICE;
+        lk.lock();
+        const int64_t per = sl.reqs.empty() ? 0 : st.n_blocks / (int64_t)sl.reqs.size();
+        for (auto& r : sl.reqs) r->n_blocks = per;
+        if (s != FSE_OK)
+            finish_slot(S, sl, s);
+        else
+            sl.launched = true;
+        S->cv.notify_all();
+    }
 }
 
 static void scheduler(fse_server* S) {
@@ -280,7 +328,21 @@ fse_status_t fse_serve_create(const fse_serve_config_t* cfg, fse_server_t** serv
             if (!sl.stream || hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess)
                 return FSE_ERR_DEVICE;
         }
-        S->worker = std::thread(scheduler, S);
+        // the slot threads, then the scheduler; threads already started are
+        // stopped and joined if a later one cannot be started
+        size_t started = 0;
+        try {
+            for (; started < S->slots.size(); ++started) S->slots[started].thread = std::thread(slot_thread, S, started);
+            S->worker = std::thread(scheduler, S);
+        } catch (...) {
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->stop_slots = true;
+                S->slot_cv.notify_all();
+            }
+            for (size_t i = 0; i < started; ++i) S->slots[i].thread.join();
+            throw;
+        }
         *server = holder.release();
         return FSE_OK;
     });
@@ -390,6 +452,13 @@ fse_status_t fse_serve_destroy(fse_server_t* S) {
             S->cv.notify_all();
         }
         if (S->worker.joinable()) S->worker.join();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop_slots = true;
+            S->slot_cv.notify_all();
+        }
+        for (auto& sl : S->slots)
+            if (sl.thread.joinable()) sl.thread.join();
         int prev_dev = 0;
         (void)hipGetDevice(&prev_dev);
         (void)hipSetDevice(S->cfg.device);

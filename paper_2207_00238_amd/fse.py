@@ -27,6 +27,7 @@ FSE_ERR_CANCELLED = -9
 FSE_PREC_F64, FSE_PREC_F32, FSE_PREC_BF16X3 = 0, 1, 2
 FSE_SCHED_PERSISTENT, FSE_SCHED_WAVEFRONT, FSE_SCHED_PER_BLOCK = 0, 1, 2
 FSE_WHOLE, FSE_TILED, FSE_TILED_VERTICAL = 0, 1, 2
+FSE_ORDER_RASTER, FSE_ORDER_OPTIMIZED = 0, 1
 FSE_MAX_CLASSES = 3
 
 EXPORTED = [
@@ -34,6 +35,7 @@ EXPORTED = [
     "fse_last_stats", "fse_release", "fse_serve_create", "fse_serve_submit", "fse_serve_poll", "fse_serve_wait",
     "fse_serve_destroy", "fse_plan_create", "fse_plan_execute", "fse_plan_destroy", "fse_plan_stats",
     "fse_autotune", "fse_plan_tiles_vertical", "fse_serve_cancel", "fse_extrapolate_noalloc",
+    "fse_autotune_overlapped",
 ]
 
 FSE_NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -66,6 +68,7 @@ class fse_params_t(ctypes.Structure):
         ("n_tiles", ctypes.c_int32), ("overlap", ctypes.c_int32), ("align", ctypes.c_int32),
         ("workgroups", ctypes.c_int32), ("block_waves", ctypes.c_int32),
         ("trace_sel", ctypes.c_void_p), ("trace_stride", ctypes.c_int32), ("trace_capacity", ctypes.c_int64),
+        ("order", ctypes.c_int32),
     ]
 
 
@@ -134,6 +137,9 @@ def lib():
         L.fse_autotune.restype = st
         L.fse_autotune.argtypes = [ctypes.c_int32, P(fse_image_t), P(fse_mask_t), P(fse_params_t), P(fse_image_t),
                                    ctypes.c_void_p, P(fse_params_t)]
+        L.fse_autotune_overlapped.restype = st
+        L.fse_autotune_overlapped.argtypes = [ctypes.c_int32, P(fse_image_t), P(fse_mask_t), P(fse_params_t),
+                                              P(fse_image_t), ctypes.c_int32, P(fse_params_t)]
         L.fse_plan_create.restype = st
         L.fse_plan_create.argtypes = [ctypes.c_int32, P(fse_mask_t), P(fse_params_t), P(ctypes.c_void_p)]
         L.fse_plan_execute.restype = st
@@ -337,7 +343,8 @@ def fse_plan_destroy(plan) -> None:
 
 
 def fse_autotune(images, masks, params: fse_params_t, outs, stream=None) -> fse_params_t:
-    """Fastest schedule (block_waves, workgroups) for this batch; outs receive results."""
+    """Fastest schedule (n_tiles when 0 in a tiled mode, block_waves,
+    workgroups) for this batch; outs receive results."""
     n = len(images)
     ims = (fse_image_t * n)(*[_image(t) for t in images])
     mks = (fse_mask_t * n)(*[_mask(t) for t in masks])
@@ -345,4 +352,16 @@ def fse_autotune(images, masks, params: fse_params_t, outs, stream=None) -> fse_
     best = fse_params_t()
     check(lib().fse_autotune(n, ims, mks, ctypes.byref(params), ots, _stream(stream), ctypes.byref(best)),
           "fse_autotune")
+    return best
+
+
+def fse_autotune_overlapped(images, masks, params: fse_params_t, outs, streams: int) -> fse_params_t:
+    """Fastest schedule for `streams` consecutive calls in flight; outs receive results."""
+    n = len(images)
+    ims = (fse_image_t * n)(*[_image(t) for t in images])
+    mks = (fse_mask_t * n)(*[_mask(t) for t in masks])
+    ots = (fse_image_t * n)(*[_image(t) for t in outs])
+    best = fse_params_t()
+    check(lib().fse_autotune_overlapped(n, ims, mks, ctypes.byref(params), ots, streams, ctypes.byref(best)),
+          "fse_autotune_overlapped")
     return best

@@ -1,23 +1,34 @@
 // Host planner of libfse driven from the command line, for CPU tests (built
 // with g++ and the address and undefined-behaviour sanitizers):
-//   plan_harness MASKFILE W H B1 b1 [B2 b2 [B3 b3]]
+//   plan_harness MASKFILE W H [opt RHO DELTA] B1 b1 [B2 b2 [B3 b3]]
 // MASKFILE holds W*H bytes (row-major, 1 = lost).  Prints
 //   "blocks N", then per block "y0 x0 class level", then "owner" and the
-// fine-cell owner map row by row.
+// fine-cell owner map row by row.  With "opt", the blocks are in the
+// optimised processing order (and numbered so), with its dependency levels.
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "fse_plan.h"
 
 int main(int argc, char** argv) {
-    if (argc < 6 || (argc - 4) % 2 != 0) {
-        std::fprintf(stderr, "usage: plan_harness MASKFILE W H B1 b1 [B2 b2 [B3 b3]]\n");
+    int first = 4;
+    bool opt = false;
+    double rho = 0.8, delta = 0.5;
+    if (argc > 7 && std::string(argv[4]) == "opt") {
+        opt = true;
+        rho = std::atof(argv[5]);
+        delta = std::atof(argv[6]);
+        first = 7;
+    }
+    if (argc < first + 2 || (argc - first) % 2 != 0) {
+        std::fprintf(stderr, "usage: plan_harness MASKFILE W H [opt RHO DELTA] B1 b1 [B2 b2 [B3 b3]]\n");
         return 2;
     }
     const int W = std::atoi(argv[2]), H = std::atoi(argv[3]);
     std::vector<fse::ClassCfg> cls;
-    for (int i = 4; i + 1 < argc; i += 2) {
+    for (int i = first; i + 1 < argc; i += 2) {
         const int B = std::atoi(argv[i]), b = std::atoi(argv[i + 1]);
         cls.push_back({B, b, 1, B + 2 * b});
     }
@@ -36,7 +47,12 @@ int main(int argc, char** argv) {
     }
     int reach = 0;
     for (auto& c : cls) reach = c.b > reach ? c.b : reach;
-    fse::plan_levels(P, cls, reach, S.cell_level);
+    if (opt) {
+        fse::OrderScratch O;
+        fse::plan_priority_order(P, mask.data(), W, cls, rho, delta, O, 4);
+    } else {
+        fse::plan_levels(P, cls, reach, S.cell_level);
+    }
     const size_t n = P.desc.size() / 4;
     std::printf("blocks %zu\n", n);
     for (size_t j = 0; j < n; ++j)

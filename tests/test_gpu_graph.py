@@ -4,6 +4,8 @@ image contents under fixed masks."""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
+
 from paper_2207_00238_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -58,10 +60,10 @@ def test_autotune_returns_equivalent_schedule():
     wl = synth.workload("small")
     img = torch.from_numpy(wl.image).to(dev)
     msk = torch.from_numpy(wl.mask).to(dev)
-    p = fse.fse_params_default(classes=wl.classes)
+    p = fse.fse_params_default(classes=wl.classes, block_waves=0)
     out_a = torch.empty_like(img)
     best = fse.fse_autotune([img], [msk], p, [out_a])
-    assert best.block_waves in (2, 4) and best.workgroups >= 0
+    assert best.block_waves in (1, 2, 4) and best.workgroups >= 0
     out_b = torch.empty_like(img)
     fse.fse_extrapolate(img, msk, best, out_b)
     torch.cuda.synchronize()
@@ -97,3 +99,85 @@ def test_plan_stats_reports_the_error_word(monkeypatch):
             assert (st["device_error"] != 0) == expect_error
         finally:
             fse.fse_plan_destroy(plan)
+
+
+def test_autotuned_tile_count_matches_the_tile_oracle():
+    # n_tiles = 0 asks the tuner for the tile count N of Algorithm 1 as well;
+    # the tuned schedule's result is the tile framework's with that N
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    W, H = 200, 136
+    imgn = synth.synth_image(W, H, seed=951, period_max=128.0)
+    mskn = synth.mask_blocks_and_pixels(W, H, 4, 0.25, 0.01, seed=952)
+    img = torch.from_numpy(imgn).to(dev)
+    msk = torch.from_numpy(mskn).to(dev)
+    cls = ((4, 14, 40),)
+    p = fse.fse_params_default(classes=cls, tiling=fse.FSE_TILED, n_tiles=0, overlap=16, align=16)
+    out = torch.empty_like(img)
+    best = fse.fse_autotune([img], [msk], p, [out])
+    assert best.n_tiles in (16, 32, 64, 128, 256), best.n_tiles
+    assert best.overlap == 16
+    got = torch.full_like(img, -1.0)
+    fse.fse_extrapolate(img, msk, best, got)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    ref = O.image_tiled(imgn, mskn, cls, best.n_tiles, 16, 16)
+    m = mskn.astype(bool)
+    assert np.array_equal(got[~m], imgn[~m])
+    assert np.abs(got - ref)[m].max() <= 1e-3
+    # a plain call with n_tiles = 0 is refused (only the tuner picks N)
+    with pytest.raises(fse.FseError):
+        fse.fse_extrapolate(img, msk, p, torch.empty_like(img))
+
+
+def test_autotune_overlapped_keeps_results():
+    # the schedule for consecutive calls in flight on three streams: the same
+    # output as the default schedule, bit for bit
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    imgs, msks = [], []
+    for i in range(3):
+        imgs.append(torch.from_numpy(synth.synth_image(160, 120, seed=961 + 2 * i, period_max=128.0)).to(dev))
+        msks.append(torch.from_numpy(synth.mask_blocks_and_pixels(160, 120, 4, 0.25, 0.01, seed=962 + 2 * i)).to(dev))
+    p = fse.fse_params_default(classes=((4, 14, 40),))
+    outs = [torch.empty_like(t) for t in imgs]
+    best = fse.fse_autotune_overlapped(imgs, msks, p, outs, 3)
+    torch.cuda.synchronize()
+    ref = [torch.empty_like(t) for t in imgs]
+    fse.fse_extrapolate_batch(imgs, msks, p, ref)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(outs, ref))
+    got = [torch.empty_like(t) for t in imgs]
+    fse.fse_extrapolate_batch(imgs, msks, best, got)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(got, ref))
+
+
+def test_autotune_cache_keys_on_the_mask_structure():
+    # same sizes and parameters, masks of another structure (another number
+    # of blocks): tuned anew, so the second mask's call takes as long as a
+    # tuning run, while repeating the first mask returns from the cache
+    import time
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    W, H = 192, 160
+    img = torch.from_numpy(synth.synth_image(W, H, seed=971, period_max=128.0)).to(dev)
+    m1 = torch.from_numpy(synth.mask_blocks(W, H, 4, 0.2, seed=972)).to(dev)
+    m2 = torch.from_numpy(synth.mask_blocks(W, H, 4, 0.05, seed=973)).to(dev)
+    p = fse.fse_params_default(classes=((4, 14, 20),), gamma=0.55)
+    out = torch.empty_like(img)
+
+    def timed(m):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fse.fse_autotune([img], [m], p, [out])
+        return time.perf_counter() - t0
+
+    first = timed(m1)
+    again = timed(m1)
+    other = timed(m2)
+    assert again < 0.5 * first, (first, again)
+    assert other > 2 * again, (again, other)

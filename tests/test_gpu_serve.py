@@ -205,3 +205,41 @@ def test_wait_limit_error_fails_the_served_request(monkeypatch):
     ref = O.image(img, mask, ((4, 14, 30),))
     m = mask.astype(bool)
     assert np.abs(o2.cpu().numpy() - ref)[m].max() <= TIGHT
+
+
+def test_trace_requests_against_the_oracle():
+    # seeded requests of the serving trace (Poisson arrivals, square sides of
+    # 512..4096, two mask kinds): the first 512 x 512 requests of the trace,
+    # each with its own image and mask, served together with a 1024 x 1024
+    # request of the same trace, every 512 x 512 result within the parity bar
+    # of the FP64 oracle (its level-parallel form, bitwise the raster oracle)
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    trace = synth.poisson_trace(200.0, 2.0, seed=31)
+    small = [r for r in trace if r["side"] == 512][:3]
+    big = [r for r in trace if r["side"] == 1024][:1]
+    assert len(small) == 3 and len(big) == 1
+    cls = ((4, 14, 100),)
+    p = fse.fse_params_default(classes=cls)
+    reqs = []
+    for r in small + big:
+        img, mask = synth.request_inputs(r)
+        ti = torch.from_numpy(img).to(dev)
+        tm = torch.from_numpy(mask).to(dev)
+        reqs.append((r, img, mask, ti, tm, torch.full_like(ti, -1.0)))
+    torch.cuda.synchronize()
+    srv = fse.fse_serve_create(hbm_budget_bytes=4 << 30, max_slots=2)
+    try:
+        tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for (_, _, _, ti, tm, o) in reqs]
+        for t in tickets:
+            fse.fse_serve_wait(srv, t, 120_000_000)
+    finally:
+        fse.fse_serve_destroy(srv)
+    for (r, img, mask, _, _, o) in reqs[:3]:
+        print("request", r["image_seed"], r["kind"], flush=True)
+        ref, _, _ = O.image_levels(img, mask, cls)
+        got = o.cpu().numpy()
+        m = mask.astype(bool)
+        assert np.array_equal(got[~m], img[~m])
+        assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT

@@ -20,7 +20,7 @@ CLASSES = [((4, 14, 1),), ((8, 28, 1), (4, 14, 1)), ((16, 24, 1), (8, 28, 1), (4
 @pytest.fixture(scope="module")
 def harness(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("plan") / "plan_harness")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-pthread", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined", "-I" + CSRC, os.path.join(ROOT, "tests", "plan_harness.cpp"),
            os.path.join(CSRC, "fse_plan.cpp"), "-o", exe]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
@@ -45,11 +45,13 @@ def _mask(seed):
     return mask, cls
 
 
-def _run(exe, tmp_path, mask, cls):
+def _run(exe, tmp_path, mask, cls, opt=None):
     H, W = mask.shape
     f = tmp_path / "mask.u8"
     f.write_bytes(np.ascontiguousarray(mask).tobytes())
     args = [exe, str(f), str(W), str(H)]
+    if opt is not None:
+        args += ["opt", repr(float(opt[0])), repr(float(opt[1]))]
     for (B, b, _) in cls:
         args += [str(B), str(b)]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=9")
@@ -87,3 +89,63 @@ def test_planner_on_the_1080p_mask(harness, tmp_path):
     y, x, c, _ = O.plan(wl.mask, wl.classes)
     assert np.array_equal(blocks[:, 0], y) and np.array_equal(blocks[:, 1], x)
     assert blocks[:, 3].max() + 1 == 1259
+
+
+# ---------------------------------------------------------------------------
+# the optimised processing order (Sec. II): the planner's order is the
+# oracle's, and its levels order every dependency of that order
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(12))
+def test_planner_priority_order_matches_oracle(harness, tmp_path, seed):
+    mask, cls = _mask(seed)
+    rho, delta = ((0.8, 0.5), (1.0, 0.5), (0.9, 0.7))[seed % 3]
+    if mask.shape[0] > 20 and mask.shape[1] > 20:
+        mask[5:5 + mask.shape[0] // 3, 3:3 + mask.shape[1] // 2] = 1  # a larger hole
+    blocks, cell_owner = _run(harness, tmp_path, mask, cls, opt=(rho, delta))
+    y, x, c, owner = O.plan(mask, cls)
+    order = O.priority_order(mask, cls, rho=rho, delta=delta)
+    assert len(blocks) == len(order)
+    assert np.array_equal(blocks[:, 0], y[order]) and np.array_equal(blocks[:, 1], x[order])
+    assert np.array_equal(blocks[:, 2], c[order])
+    rank = np.argsort(order)
+    Bmin = cls[-1][0]
+    ly, lx = np.nonzero(mask)
+    assert np.array_equal(cell_owner[ly // Bmin, lx // Bmin], rank[owner[ly, lx]])
+    level = blocks[:, 3]  # by processing rank
+    preds = O.dependencies(mask, cls, order=order)
+    for j, pj in enumerate(preds):
+        for i in pj:
+            assert level[rank[i]] < level[rank[j]], (i, j)
+    # and exactly the longest chain of the kernel's waits: two blocks wait on
+    # each other when the bounding box of either one's lost pixels meets the
+    # other's window (brute force over all pairs, in processing order)
+    n = len(order)
+    box = np.zeros((n, 4), np.int64)
+    for b in range(n):
+        ys, xs = np.nonzero(owner == b)
+        box[b] = (ys.min(), xs.min(), ys.max() + 1, xs.max() + 1)
+    win = np.array([(y[b] - cls[c[b]][1], x[b] - cls[c[b]][1], y[b] + cls[c[b]][0] + cls[c[b]][1],
+                     x[b] + cls[c[b]][0] + cls[c[b]][1]) for b in range(n)], np.int64).reshape(n, 4)
+
+    def meet(a, b):
+        return (a[:, 0] < b[:, 2]) & (b[:, 0] < a[:, 2]) & (a[:, 1] < b[:, 3]) & (b[:, 1] < a[:, 3])
+
+    want = np.zeros(n, np.int64)
+    for k in range(n):
+        j = order[k]
+        earlier = order[:k]
+        if k:
+            hit = meet(box[earlier], win[[j] * k]) | meet(box[[j] * k], win[earlier])
+            if hit.any():
+                want[j] = want[earlier[hit]].max() + 1
+    assert np.array_equal(level, want[order])
+
+
+def test_planner_priority_order_on_the_1080p_mask(harness, tmp_path):
+    # the benchmark's mask: the same order as the oracle at full size
+    wl = synth.workload("hd", 0)
+    blocks, _ = _run(harness, tmp_path, wl.mask, wl.classes, opt=(0.8, 0.5))
+    y, x, _, _ = O.plan(wl.mask, wl.classes)
+    order = O.priority_order(wl.mask, wl.classes)
+    assert np.array_equal(blocks[:, 0], y[order]) and np.array_equal(blocks[:, 1], x[order])
+    print("levels: optimised order", blocks[:, 3].max() + 1)

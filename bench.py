@@ -98,6 +98,22 @@ def traffic_from_profiles(workload: str, n_launch_units: float):
     return rec.get("hbm_bytes_per_launch")
 
 
+def phases_from_profiles(workload: str):
+    """Per-phase roofline figures of the block kernel from the committed
+    rocprofv3 summaries (the DFT phase from a K = 0 launch with MFMA
+    counters, the selection loop's LDS and VALU figures from the counters of
+    the K = 100 launch), when they were taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"phases_fse_blocks_{workload}.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return {k: rec[k] for k in ("dft_phase", "loop", "profiles") if k in rec}
+
+
 def cpu_baseline():
     """The FP64 oracle, single thread, on the top-left 1280x720 crop of the
     workload's first image and mask (the crop is processed as an image of its
@@ -353,7 +369,8 @@ def main():
                      "kernel": f"k_fse_blocks<{params.block_waves or 4}>", "flops_per_block": flops,
                      # the same work over the overlapped timed steps (launches share the device there)
                      "achieved_overlapped": n_blocks * flops * args.steps / total / 1e12,
-                     "frac_overlapped": n_blocks * flops * args.steps / total / 1e12 / MI355X_FP64_VECTOR_TFLOPS},
+                     "frac_overlapped": n_blocks * flops * args.steps / total / 1e12 / MI355X_FP64_VECTOR_TFLOPS,
+                     "phases": phases_from_profiles("hd")},
     }
 
     progress("pipelined steps done")

@@ -243,3 +243,33 @@ def test_trace_requests_against_the_oracle():
         m = mask.astype(bool)
         assert np.array_equal(got[~m], img[~m])
         assert np.abs(got.astype(np.float64) - ref)[m].max() <= TIGHT
+
+
+def test_sixteen_slots_each_result_as_alone():
+    # the largest server: sixteen slots (each a stream with a hardware queue of
+    # its own and a planning thread), requests submitted one by one so that
+    # many groups are planned and in flight at once; every result bitwise the
+    # request alone
+    import torch
+    from paper_2207_00238_amd import fse
+    dev = torch.device("cuda:0")
+    p = fse.fse_params_default(classes=((4, 14, 40),))
+    reqs = []
+    for i in range(24):
+        W, H = 64 + 16 * (i % 5), 48 + 16 * (i % 3)
+        img, mask = _inputs(W, H, 1200 + 2 * i, "blocks" if i % 2 else "pixels")
+        ti = torch.from_numpy(img).to(dev)
+        tm = torch.from_numpy(mask).to(dev)
+        alone = torch.empty_like(ti)
+        fse.fse_extrapolate(ti, tm, p, alone)
+        reqs.append((ti, tm, torch.full_like(ti, -1.0), alone))
+    torch.cuda.synchronize()
+    srv = fse.fse_serve_create(hbm_budget_bytes=1 << 30, max_slots=16)
+    try:
+        tickets = [fse.fse_serve_submit(srv, ti, tm, p, o) for (ti, tm, o, _) in reqs]
+        for t in tickets:
+            fse.fse_serve_wait(srv, t, 60_000_000)
+    finally:
+        fse.fse_serve_destroy(srv)
+    for (_, _, o, alone) in reqs:
+        assert torch.equal(o, alone)

@@ -291,7 +291,7 @@ void run_chunks(int n, int nt, F&& fn) {
 struct ShareHeap {
     const int64_t* full;  // per class
     HeapEntry* heap;
-    int32_t* pos;         // entry of every block, -1 once popped
+    int32_t* pos;         // entry of every block (stride 2), -1 once popped
     int n = 0;
     bool one_full = false;  // every class has the same full-window weight: compare shares directly
     bool above(const HeapEntry& a, const HeapEntry& b) const {
@@ -302,7 +302,7 @@ struct ShareHeap {
     }
     void place(int k, const HeapEntry& e) {
         heap[k] = e;
-        pos[e.id] = k;
+        pos[2 * e.id] = k;
     }
     void up(int k) {
         const HeapEntry e = heap[k];
@@ -328,12 +328,12 @@ struct ShareHeap {
     }
     // block i's share grows by d
     void raise(int i, int64_t d) {
-        heap[pos[i]].share += d;
-        up(pos[i]);
+        heap[pos[2 * i]].share += d;
+        up(pos[2 * i]);
     }
     int pop() {
         const int top = heap[0].id;
-        pos[top] = -1;
+        pos[2 * top] = -1;
         if (--n > 0) {
             place(0, heap[n]);
             down(0);
@@ -395,20 +395,34 @@ void plan_priority_order(RegionPlan& P, const uint8_t* mask, int64_t pitch, cons
         if (m1 <= m0 || k1 <= k0) return 0;
         return pre[m1 * (M + 1) + k1] - pre[m0 * (M + 1) + k1] - pre[m1 * (M + 1) + k0] + pre[m0 * (M + 1) + k0];
     };
-    // lost pixels of every block, grouped by block
-    S.lost_off.resize(n + 1);
-    S.lost_yx.clear();
-    for (int j = 0; j < n; ++j) {
-        S.lost_off[j] = (int32_t)(S.lost_yx.size() / 2);
-        const int32_t* lb = &P.lbox[4 * j];
+    const int nth = std::max(1, std::min(threads, n / 256 + 1));
+    // lost pixels of every block, grouped by block: counted, then filled, by
+    // chunks of blocks on threads of their own
+    auto lost_scan = [&](int j, auto&& fn) {
+        const int32_t* lb = &P.lbox[4 * (size_t)j];
         for (int y = lb[0]; y < lb[2]; ++y)
             for (int x = lb[1]; x < lb[3]; ++x)
-                if (mask[(int64_t)y * pitch + x] && P.owner[(size_t)(y / Bmin) * P.fw + x / Bmin] == j) {
-                    S.lost_yx.push_back(y);
-                    S.lost_yx.push_back(x);
-                }
-    }
-    S.lost_off[n] = (int32_t)(S.lost_yx.size() / 2);
+                if (mask[(int64_t)y * pitch + x] && P.owner[(size_t)(y / Bmin) * P.fw + x / Bmin] == j) fn(y, x);
+    };
+    S.lost_off.assign(n + 1, 0);
+    run_chunks(n, nth, [&](int, int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            int cnt = 0;
+            lost_scan(j, [&](int, int) { ++cnt; });
+            S.lost_off[j + 1] = cnt;
+        }
+    });
+    for (int j = 0; j < n; ++j) S.lost_off[j + 1] += S.lost_off[j];
+    S.lost_yx.resize(2 * (size_t)S.lost_off[n]);
+    run_chunks(n, nth, [&](int, int j0, int j1) {
+        for (int j = j0; j < j1; ++j) {
+            int32_t* out = S.lost_yx.data() + 2 * (size_t)S.lost_off[j];
+            lost_scan(j, [&](int y, int x) {
+                *out++ = y;
+                *out++ = x;
+            });
+        }
+    });
     // every block i whose window meets the lost pixels of block j:
     // fn(i, sum over those pixels of table t of i's class, at their window
     // positions); table 0 = known weights, 1 = reconstructed weights
@@ -486,7 +500,6 @@ void plan_priority_order(RegionPlan& P, const uint8_t* mask, int64_t pitch, cons
     // of i's reconstructed weights over j's lost pixels (what i's share gains
     // when j is processed).  Counted, then filled in place, by chunks of
     // blocks on threads of their own.
-    const int nth = std::max(1, std::min(threads, n / 256 + 1));
     S.adj_off.assign(n + 1, 0);
     run_chunks(n, nth, [&](int, int j0, int j1) {
         for (int j = j0; j < j1; ++j) {
@@ -541,48 +554,65 @@ void plan_priority_order(RegionPlan& P, const uint8_t* mask, int64_t pitch, cons
     // before it (and from the raises it received from earlier blocks whose
     // lists hold it), then raises the listed blocks still to come.
     S.heap.resize(n);
-    S.pos.resize(n);
+    S.pos.resize(2 * (size_t)n);  // per block: heap entry (-1 once processed), level
     ShareHeap hp{full.data(), S.heap.data(), S.pos.data(), n};
     hp.one_full = std::all_of(full.begin(), full.end(), [&](int64_t f) { return f == full[0]; });
-    for (int i = 0; i < n; ++i) hp.place(i, HeapEntry{S.share[i], i, desc[4 * i + 2]});
+    for (int i = 0; i < n; ++i) {
+        hp.place(i, HeapEntry{S.share[i], i, desc[4 * i + 2]});
+        S.pos[2 * (size_t)i + 1] = 0;
+    }
     for (int k = n / 2 - 1; k >= 0; --k) hp.down(k);
     S.perm.resize(n);
-    S.level.assign(n, 0);
     const int32_t* aoff = S.adj_off.data();
     const int32_t* ai = S.adj_i.data();
     const int64_t* as = S.adj_s.data();
-    int32_t* pos = S.pos.data();
-    int32_t* lev = S.level.data();
+    int32_t* pl = S.pos.data();
+    int deg = 0;
+    for (int j = 0; j < n; ++j) deg = std::max(deg, aoff[j + 1] - aoff[j]);
+    S.tmp.resize(deg);
+    S.pend.resize(deg);
+    int32_t* pend_i = S.tmp.data();
+    int64_t* pend_s = S.pend.data();
     for (int k = 0; k < n; ++k) {
-        const int j = hp.pop();  // pos[j] = -1 from here on
+        const int j = hp.pop();  // its heap entry is -1 from here on
         S.perm[k] = j;
-        int lv = lev[j];
+        // one pass over j's list: the level from the blocks processed before
+        // it, and the blocks still to come
+        int lv = pl[2 * j + 1], np = 0;
         for (int e = aoff[j]; e < aoff[j + 1]; ++e) {
             const int i = ai[e];  // (j's own window meets its lost box: j is in its list)
-            if (i != j && pos[i] < 0 && lev[i] + 1 > lv) lv = lev[i] + 1;
+            if (pl[2 * i] < 0) {
+                if (i != j && pl[2 * i + 1] + 1 > lv) lv = pl[2 * i + 1] + 1;
+            } else {
+                pend_i[np] = i;
+                pend_s[np++] = as[e];
+            }
         }
-        lev[j] = lv;
-        for (int e = aoff[j]; e < aoff[j + 1]; ++e) {
-            const int i = ai[e];
-            if (pos[i] < 0) continue;  // processed already (or j itself)
-            if (lev[i] < lv + 1) lev[i] = lv + 1;
-            if (as[e] != 0) hp.raise(i, as[e]);
+        pl[2 * j + 1] = lv;
+        for (int u = 0; u < np; ++u) {
+            const int i = pend_i[u];
+            if (pl[2 * i + 1] < lv + 1) pl[2 * i + 1] = lv + 1;
+            if (pend_s[u] != 0) hp.raise(i, pend_s[u]);
         }
     }
     S.rank.resize(n);
     for (int k = 0; k < n; ++k) S.rank[S.perm[k]] = k;
     // renumber: block k of the plan is the k-th processed
-    for (auto& o : P.owner)
-        if (o >= 0) o = S.rank[o];
     std::vector<int32_t> d2(4 * (size_t)n), l2(4 * (size_t)n);
     P.level.resize(n);
-    for (int k = 0; k < n; ++k) {
-        for (int q = 0; q < 4; ++q) {
-            d2[4 * k + q] = P.desc[4 * (size_t)S.perm[k] + q];
-            l2[4 * k + q] = P.lbox[4 * (size_t)S.perm[k] + q];
+    const int no = (int)P.owner.size();
+    run_chunks(std::max(n, no), nth, [&](int, int k0, int k1) {
+        for (int c = k0; c < std::min(k1, no); ++c)
+            if (P.owner[c] >= 0) P.owner[c] = S.rank[P.owner[c]];
+        for (int k = k0; k < std::min(k1, n); ++k) {
+            const size_t src = 4 * (size_t)S.perm[k];
+            for (int q = 0; q < 4; ++q) {
+                d2[4 * (size_t)k + q] = P.desc[src + q];
+                l2[4 * (size_t)k + q] = P.lbox[src + q];
+            }
+            P.level[k] = S.pos[2 * (size_t)S.perm[k] + 1];
         }
-        P.level[k] = S.level[S.perm[k]];
-    }
+    });
     P.desc.swap(d2);
     P.lbox.swap(l2);
     P.key = P.level;

@@ -34,7 +34,7 @@ struct RegionPlan {
 struct OrderScratch {
     std::vector<int64_t> share;     // per block: usable window weight (exact integer)
     std::vector<HeapEntry> heap;  // max-heap of the blocks not yet processed
-    std::vector<int32_t> pos;     // heap entry of every block
+    std::vector<int32_t> pos;     // per block, interleaved: heap entry (-1 once processed), dependency level
     std::vector<int32_t> lost_off;  // per block: start of its lost pixels in lost_yx
     std::vector<int32_t> lost_yx;   // lost pixels, (y, x) pairs, grouped by block
     std::vector<int32_t> adj_off;   // per block j: start of its pairs
@@ -42,8 +42,8 @@ struct OrderScratch {
     std::vector<int64_t> adj_s;     // and what each one's share gains when j is processed
     std::vector<int32_t> perm;      // processing order (raster indices)
     std::vector<int32_t> rank;      // position of every raster block in that order
-    std::vector<int32_t> level;     // dependency level per raster block
-    std::vector<int32_t> tmp;       // first block per corner cell
+    std::vector<int64_t> pend;      // the processed block's listed blocks still to come: their gains
+    std::vector<int32_t> tmp;       // first block per corner cell, then those blocks' numbers
     std::vector<int64_t> qtab;      // per class: known weights, reconstructed weights, prefix sums
 };
 

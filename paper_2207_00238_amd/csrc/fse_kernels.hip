@@ -380,7 +380,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const double* tws = (M == 32) ? H.tws32 : tw64 + 64;
     const int t = threadIdx.x;
     const int lane = t & 63;
-    const int wv = t >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // in a scalar register
     const bool active = wv < NW;  // wave-uniform
     const int ti0 = TM::ti0(wv), tj0 = TM::tj0(wv);
     const int4 d = uniform_load(J.desc + blk);
@@ -744,11 +744,21 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         const int jr = (e / NTJ) & 3, jci = e / (4 * NTJ), jcj = e % NTJ;
         return (jci * 16 + ROWR * jr) * M + jcj * 16;
     };
-    if (!active) {
-        if constexpr (NW > 1)
-            for (int it = 0; it < nsteps; ++it) __syncthreads();  // the step exchanges of the active waves
-    } else
-    for (int it = 0; it < nsteps; ++it) {
+    // gather address of the shifted weight spectrum (M = 32, rows repeated,
+    // one tile per wave): one base per lane for its four rows, (row mod M,
+    // column mod M) formed as two 16-bit fields in one packed subtraction --
+    // the row field in units of a spectrum row, the column field in units of
+    // an element
+    constexpr int ES = 2 * (int)sizeof(T);  // bytes per complex element
+    constexpr bool PACKED = DUP && NTI == 1 && NTJ == 1;
+    static_assert(!PACKED || (M - 1) * M * ES < 65536, "packed gather address");
+    typedef unsigned short ushort2_v __attribute__((ext_vector_type(2)));
+    const unsigned gather_base =
+        ((unsigned)((ti0 * 16 + ROWK * lk) * M * ES) << 16) | (unsigned)((tj0 * 16 + li) * ES);
+    constexpr unsigned kGatherMask = ((unsigned)(MASK * M * ES) << 16) | (unsigned)(MASK * ES);
+    // one selection step; P is the parity of the step (double-buffered slots)
+    auto step = [&](const int it, auto parity) {
+        constexpr int P = decltype(parity)::value;
         // first-index maximum over the lane's elements (pairwise tree over
         // increasing index: the right operand wins only when strictly larger);
         // the tree carries the element's number (small constants, no
@@ -789,40 +799,53 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             ar = readlane_t(car_l, wl);
             ai = readlane_t(cai_l, wl);
         } else {
-            const int p = it & 1;
             // the winner lane publishes its own energy, index and coefficient
             if (lane == wl) {
-                H.sK[p][wv] = make_double2((double)lm, __hiloint2double(0, ix[0]));
-                H.sA[p][wv] = make_double2(car_l, cai_l);
+                H.sK[P][wv] = make_double2((double)lm, __hiloint2double(0, ix[0]));
+                H.sA[P][wv] = make_double2(car_l, cai_l);
             }
             __syncthreads();  // slots visible to every wave
             // winner among the waves (larger energy, then smaller index):
             // lane q < NW reads the slot of wave q and the lanes pick it like
             // the wave winner, on a quad instead of the whole wave
-            const double2 sk = H.sK[p][lane & (NW - 1)];
+            const double2 sk = H.sK[P][lane & (NW - 1)];
             const int wq = slot_winner<NW>(sk.x, __double2loint(sk.y));
             IDX = __builtin_amdgcn_readlane(__double2loint(sk.y), wq);
-            const double2 al = H.sA[p][wq];
+            const double2 al = H.sA[P][wq];
             ar = al.x;
             ai = al.y;
         }
         // the shifted weight spectrum for this lane's elements
         const int u = IDX >> LOGM, v = IDX & MASK;
         T wr[EPT], wi[EPT];
+        if constexpr (PACKED) {
+            const unsigned shift = ((unsigned)(u * M * ES) << 16) | (unsigned)(v * ES);
+            const ushort2_v d = __builtin_bit_cast(ushort2_v, gather_base) - __builtin_bit_cast(ushort2_v, shift);
+            const unsigned f = __builtin_bit_cast(unsigned, d) & kGatherMask;
+            const unsigned char* w0 = reinterpret_cast<const unsigned char*>(Wd) + (f >> 16) + (f & 0xffffu);
 #pragma unroll
-        for (int ci_ = 0; ci_ < NTI; ++ci_) {
+            for (int r = 0; r < 4; ++r) {
+                // rows (row0 mod M) + ROWR r lie below M + kWrapRows
+                const T* w = reinterpret_cast<const T*>(w0 + r * (ROWR * M * ES));
+                wr[r] = w[0];
+                wi[r] = w[1];
+            }
+        } else {
 #pragma unroll
-            for (int cj = 0; cj < NTJ; ++cj) {
-                const int col = ((tj0 + cj) * 16 + li - v) & MASK;
-                const int row0 = (ti0 + ci_) * 16 + ROWK * lk - u;
+            for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int e = (ci_ * 4 + r) * NTJ + cj;
-                    // DUP: rows (row0 mod M) + ROWR r lie below M + kWrapRows
-                    const T* w = DUP ? (Wd + (((row0 & MASK) << LOGM) + col) * 2 + r * (ROWR * M * 2))
-                                     : (Wd + ((((row0 + ROWR * r) & MASK) << LOGM) + col) * 2);
-                    wr[e] = w[0];
-                    wi[e] = w[1];
+                for (int cj = 0; cj < NTJ; ++cj) {
+                    const int col = ((tj0 + cj) * 16 + li - v) & MASK;
+                    const int row0 = (ti0 + ci_) * 16 + ROWK * lk - u;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int e = (ci_ * 4 + r) * NTJ + cj;
+                        // DUP: rows (row0 mod M) + ROWR r lie below M + kWrapRows
+                        const T* w = DUP ? (Wd + (((row0 & MASK) << LOGM) + col) * 2 + r * (ROWR * M * 2))
+                                         : (Wd + ((((row0 + ROWR * r) & MASK) << LOGM) + col) * 2);
+                        wr[e] = w[0];
+                        wi[e] = w[1];
+                    }
                 }
             }
         }
@@ -838,11 +861,23 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             car[it] = ar;
             cai[it] = ai;
             cidx[it] = IDX;
-            if (trace) trace[it] = IDX;
         }
+    };
+    if (!active) {
+        if constexpr (NW > 1)
+            for (int it = 0; it < nsteps; ++it) __syncthreads();  // the step exchanges of the active waves
+    } else {
+        int it = 0;
+        for (; it + 1 < nsteps; it += 2) {
+            step(it, std::integral_constant<int, 0>());
+            step(it + 1, std::integral_constant<int, 1>());
+        }
+        if (it < nsteps) step(it, std::integral_constant<int, 0>());
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
     __syncthreads();  // the coefficient list is complete
+    if (trace)
+        for (int it = t; it < nsteps; it += NT) trace[it] = cidx[it];
 
     // ---- synthesis at the block's lost pixels ------------------------------
     // gs lanes of one wave per pixel, each summing every gs-th step; B*B

@@ -762,14 +762,18 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         // first-index maximum over the lane's elements (pairwise tree over
         // increasing index: the right operand wins only when strictly larger);
         // the tree carries the element's number (small constants, no
-        // registers) and value; the spectrum index follows from the number
-        T ev[EPT], vr[EPT], vi[EPT];
+        // registers), with four elements per lane also its value; the
+        // spectrum index follows from the number
+        constexpr bool CARRY = EPT <= 4 || NW == 1;
+        T ev[EPT], vr[CARRY ? EPT : 1], vi[CARRY ? EPT : 1];
         int ex[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             ev[j] = rr[j] * rr[j] + ri[j] * ri[j];
-            vr[j] = rr[j];
-            vi[j] = ri[j];
+            if constexpr (CARRY) {
+                vr[j] = rr[j];
+                vi[j] = ri[j];
+            }
             ex[j] = j;
         }
 #pragma unroll
@@ -779,19 +783,34 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                 const bool take = ev[j + st] > ev[j];
                 ev[j] = take ? ev[j + st] : ev[j];
                 ex[j] = take ? ex[j + st] : ex[j];
-                vr[j] = take ? vr[j + st] : vr[j];
-                vi[j] = take ? vi[j + st] : vi[j];
+                if constexpr (CARRY) {
+                    vr[j] = take ? vr[j + st] : vr[j];
+                    vi[j] = take ? vi[j + st] : vi[j];
+                }
             }
         }
         const T lm = ev[0];
         int ix[1] = {lane_idx + elem_offset(ex[0])};
-        // the lane's candidate coefficient, formed before the wave reduction
-        // so that it is ready when the winner lane publishes it (the empty
-        // asm keeps it from being sunk into the winner's branch)
-        double car_l = g * (double)vr[0], cai_l = g * (double)vi[0];
-        asm volatile("" : "+v"(car_l), "+v"(cai_l));
+        double car_l, cai_l;
+        if constexpr (CARRY) {
+            // the lane's candidate coefficient, formed before the wave
+            // reduction so that it is ready when the winner lane publishes
+            // it (the empty asm keeps it from being sunk into the winner's
+            // branch)
+            car_l = g * (double)vr[0];
+            cai_l = g * (double)vi[0];
+            asm volatile("" : "+v"(car_l), "+v"(cai_l));
+        }
         // winner lane of the wave: largest energy, then smallest index
         const int wl = wave_argmax_lane(lm, [&] { return ix[0]; });
+        if constexpr (!CARRY) {
+            // more elements per lane: the winner's element number in a scalar
+            // register selects its value by register index, instead of a
+            // select per tree node and element
+            const int ew = __builtin_amdgcn_readlane(ex[0], wl);
+            car_l = g * (double)rr[ew];
+            cai_l = g * (double)ri[ew];
+        }
         int IDX;
         double ar, ai;
         if constexpr (NW == 1) {

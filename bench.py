@@ -111,7 +111,7 @@ def phases_from_profiles(workload: str):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return {k: rec[k] for k in ("dft_phase", "loop", "profiles") if k in rec}
+    return {k: rec[k] for k in ("dft_phase", "loop", "optimized_order_batch", "profiles") if k in rec}
 
 
 def end_to_end_with_copies(fse, torch, imgs, msks, outs, params, stream, n_blocks, steps):

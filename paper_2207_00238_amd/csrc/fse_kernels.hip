@@ -152,7 +152,7 @@ struct SharedHead {
 };
 
 // 32 x 32 launches: the head and the buffer (32 KB in all, so the LDS of a CU
-// holds five blocks; the 128-VGPR bound of the FP64 kernel holds four).
+// holds five blocks, as does the 96-VGPR bound of the 4-wave kernels).
 // Launches with 64 x 64 windows add the 64-point twiddles.
 struct Shared32 {
     SharedHead h;
@@ -994,10 +994,10 @@ __device__ void wait_predecessors(const LaunchArgs& a, const JobDev& J, int blk)
 // each block branches on its window size).
 template <int NW, int PREC, bool WIDE>
 // Occupancy (the second bound counts waves per SIMD): the 4-wave 32 x 32
-// kernel holds four blocks per CU (128 VGPRs); the FP64 kernel of launches
+// kernels hold five blocks per CU (96 VGPRs); the FP64 kernel of launches
 // with 64 x 64 windows two (eight waves each, so four per SIMD: 128 VGPRs;
 // 73 KB of LDS each).
-__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) || (WIDE && PREC == 0) ? 4 : 1)
+__global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 5 : (WIDE && PREC == 0) ? 4 : 1)
     k_fse_blocks(LaunchArgs a, int ticket_base) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SharedHead& H = *reinterpret_cast<SharedHead*>(smem_raw);

@@ -1006,9 +1006,12 @@ fse_status_t autotune(int32_t n, const fse_image_t* images, const fse_mask_t* ma
     int best_w = waves.back(), best_g = 0;
     for (int w : waves) {
         const int cap = persistent_grid(wide ? kWideWaves : w, p->precision, wide);
+        // fixed sizes and fractions of the resident capacity (launches in
+        // flight share it), each once
         std::vector<int> grids{0};
-        for (int g : {128, 256, 384, 512, 768, 1024})
-            if (g < cap) grids.push_back(g);
+        for (int g : {128, 256, 384, 512, 768, 1024, cap / 4, cap / 2, 3 * cap / 4})
+            if (g > 0 && g < cap && std::find(grids.begin(), grids.end(), g) == grids.end()) grids.push_back(g);
+        std::sort(grids.begin() + 1, grids.end());
         grids.push_back(cap);
         for (int g : grids) {
             fse_params_t q = cur;

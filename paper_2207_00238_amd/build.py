@@ -21,6 +21,9 @@ FLAGS = [
     "-shared",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # atomics stay as written: the selection steps' one-lane LDS maximum is
+    # not turned into a wave reduction loop
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-result", "-Wno-unused-value",
     "-I" + os.path.join(ROOT, "include"),
 ]

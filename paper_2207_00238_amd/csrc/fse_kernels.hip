@@ -143,9 +143,10 @@ constexpr int kBufDoubles64 = 2 * 64 * 65 + 2 * kMaxK + kMaxK / 2;
 struct SharedHead {
     double twc32[32], tws32[32];
     double part[8];
-    // per step (double-buffered) and wave: the wave winner's energy, spectrum
-    // index and coefficient
-    double2 sK[2][8];  // energy, index (low word)
+    // per step (three in rotation): the maximum over the waves of the wave
+    // winner's energy with its last 12 bits replaced by 4095 - its index
+    unsigned long long kmax[3];
+    // per step (double-buffered) and wave: the wave winner's coefficient
     double2 sA[2][8];
     int job, blk;
     uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
@@ -201,11 +202,12 @@ __device__ __forceinline__ int wave_argmax_lane(double e, IndexFn idx_of) {
         cand = cand && lo == mlo;
         bal = __ballot(cand);
         if (__popcll(bal) > 1) {
-            // exact tie between lanes: the smallest spectrum index among them
-            const int idx = idx_of();
-            int best = cand ? idx : 0x7fffffff;
-            for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
-            bal = __ballot(cand && idx == best);
+            // exact tie between lanes: the smallest spectrum index among them,
+            // as the DPP maximum of its complement (no shuffle addresses to
+            // keep in registers)
+            const unsigned inv = cand ? ~(unsigned)idx_of() : 0u;
+            const unsigned minv = wave_umax(inv);  // with every lane active
+            bal = __ballot(cand && inv == minv);
         }
     }
     return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
@@ -217,42 +219,9 @@ __device__ __forceinline__ int wave_argmax_lane(float e, IndexFn idx_of) {
     const bool cand = k == wave_umax(k);
     uint64_t bal = __ballot(cand);
     if (__popcll(bal) > 1) {
-        const int idx = idx_of();
-        int best = cand ? idx : 0x7fffffff;
-        for (int off = 32; off >= 1; off >>= 1) best = min(best, __shfl_xor(best, off));
-        bal = __ballot(cand && idx == best);
-    }
-    return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
-}
-
-// Winner among NW <= 8 wave slots held by lanes 0..NW-1 (energy e >= 0,
-// index idx): largest energy, then smallest index.  Maxima over the first NW
-// lanes by DPP; lanes >= NW are ignored.
-template <int NW>
-__device__ __forceinline__ int slot_winner(double e, int idx) {
-    constexpr unsigned long long SM = (1ull << NW) - 1;
-    auto quad_umax = [](unsigned v) {
-        if constexpr (NW >= 2) v = dpp_umax_step<0xB1, 0xF, 0xF>(v);   // quad_perm [1,0,3,2]
-        if constexpr (NW >= 4) v = dpp_umax_step<0x4E, 0xF, 0xF>(v);   // quad_perm [2,3,0,1]
-        if constexpr (NW >= 8) v = dpp_umax_step<0x141, 0xF, 0xF>(v);  // row_half_mirror
-        return (unsigned)__builtin_amdgcn_readlane((int)v, 0);
-    };
-    const unsigned hi = (unsigned)__double2hiint(e);
-    bool cand = hi == quad_umax(hi);
-    uint64_t bal = __ballot(cand) & SM;
-    // (each DPP maximum is taken with every lane active: evaluated before
-    // the lane's own condition, never under it)
-    if (__popcll(bal) > 1) {
-        const unsigned lo = (unsigned)__double2loint(e);
-        const unsigned mlo = quad_umax(cand ? lo : 0u);
-        cand = cand && lo == mlo;
-        bal = __ballot(cand) & SM;
-        if (__popcll(bal) > 1) {
-            // equal energies: the smallest index (as a maximum of its complement)
-            const unsigned inv = cand ? ~(unsigned)idx : 0u;
-            const unsigned minv = quad_umax(inv);
-            bal = __ballot(cand && inv == minv) & SM;
-        }
+        const unsigned inv = cand ? ~(unsigned)idx_of() : 0u;
+        const unsigned minv = wave_umax(inv);  // with every lane active
+        bal = __ballot(cand && inv == minv);
     }
     return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
 }
@@ -344,11 +313,23 @@ struct TileMap {
     static constexpr int NTJ = (M == 32) ? ((NW == 1) ? 2 : 1) : ((NW <= 4) ? 4 / NW : 1);
     // row tiles per wave
     static constexpr int NTI = (M == 32) ? ((NW == 4) ? 1 : 2) : ((NW <= 4) ? 4 : 2);
-    __device__ static int ti0(int wv) {
+    __host__ __device__ static constexpr int ti0(int wv) {
         return (M == 32) ? ((NW == 4) ? (wv >> 1) : 0) : ((NW == 8) ? (wv >> 2) * 2 : 0);
     }
-    __device__ static int tj0(int wv) {
+    __host__ __device__ static constexpr int tj0(int wv) {
         return (M == 32) ? ((NW == 4) ? (wv & 1) : (NW == 2 ? wv : 0)) : ((NW == 8) ? (wv & 3) : wv * NTJ);
+    }
+    // the wave that owns spectrum tile (row tile rt, column tile ct)
+    __host__ __device__ static constexpr int wave_of(int rt, int ct) {
+        return (M == 32) ? ((NW == 4) ? ((rt << 1) | ct) : (NW == 2 ? ct : 0))
+                         : ((NW == 8) ? (((rt >> 1) << 2) | ct) : ct / NTJ);
+    }
+    static constexpr bool wave_of_inverts() {
+        for (int w = 0; w < NW; ++w)
+            for (int i = 0; i < NTI; ++i)
+                for (int j = 0; j < NTJ; ++j)
+                    if (wave_of(ti0(w) + i, tj0(w) + j) != w) return false;
+        return true;
     }
 };
 
@@ -715,6 +696,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     } else {
         dft(0);  // R
     }
+    if (t == 0) H.kmax[0] = H.kmax[1] = H.kmax[2] = 0ull;  // the steps' maxima
     __syncthreads();
 
     // ---- K greedy steps ----------------------------------------------------
@@ -818,18 +800,27 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             ar = readlane_t(car_l, wl);
             ai = readlane_t(cai_l, wl);
         } else {
-            // the winner lane publishes its own energy, index and coefficient
+            // the block winner through one 64-bit LDS maximum: each wave's
+            // winner lane enters its non-negative energy (whose bit pattern
+            // orders like its value) with the last 12 bits replaced by
+            // 4095 - its index, so equal energies, and energies within 2^-40
+            // of each other, go to the smaller index; and it publishes its
+            // coefficient.  Three maxima rotate: the one of the step after
+            // this is cleared now (its last readers, two steps back, have all
+            // passed the previous barrier).
+            static_assert(TM::wave_of_inverts(), "tile owner");
+            const int ks = it % 3, kn = (it + 1) % 3;
             if (lane == wl) {
-                H.sK[P][wv] = make_double2((double)lm, __hiloint2double(0, ix[0]));
+                const unsigned long long key =
+                    ((unsigned long long)__double_as_longlong((double)lm) & ~0xFFFull) | (unsigned long long)(unsigned)(0xFFF - ix[0]);
+                atomicMax(&H.kmax[ks], key);
                 H.sA[P][wv] = make_double2(car_l, cai_l);
             }
-            __syncthreads();  // slots visible to every wave
-            // winner among the waves (larger energy, then smaller index):
-            // lane q < NW reads the slot of wave q and the lanes pick it like
-            // the wave winner, on a quad instead of the whole wave
-            const double2 sk = H.sK[P][lane & (NW - 1)];
-            const int wq = slot_winner<NW>(sk.x, __double2loint(sk.y));
-            IDX = __builtin_amdgcn_readlane(__double2loint(sk.y), wq);
+            if (t == 0) H.kmax[kn] = 0ull;
+            __syncthreads();  // the maximum and the coefficients visible to every wave
+            const unsigned long long km = H.kmax[ks];
+            IDX = 0xFFF - (__builtin_amdgcn_readfirstlane((int)(unsigned)km) & 0xFFF);
+            const int wq = TM::wave_of((IDX >> LOGM) >> 4, (IDX & MASK) >> 4);
             const double2 al = H.sA[P][wq];
             ar = al.x;
             ai = al.y;

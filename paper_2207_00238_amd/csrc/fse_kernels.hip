@@ -14,9 +14,12 @@
 //      F X F on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
 //      F[k,m] = e^{-2 pi i k m / M};
 //   4. K greedy steps: argmax of |R|^2 (ties to the smallest index),
-//      alpha = gamma R[u,v] / W0, R -= alpha * W shifted by (u,v);
+//      alpha = gamma R[u,v] / W0, R -= alpha * W shifted by (u,v) -- with
+//      the weight spectrum stored pre-scaled by gamma / W0, so a step
+//      subtracts R[u,v] times the stored spectrum and records R[u,v];
 //   5. evaluate Re sum alpha e^{+2 pi i (u m + v n)/M} at the block's lost
-//      pixels, store them (FP64 working copy and float32 output), publish.
+//      pixels (gamma / W0 times the sum over the recorded R[u,v]), store
+//      them (FP64 working copy and float32 output), publish.
 // The block model is Sec. II of the paper; the wait and the persistent
 // ticket dispatch are this library's way of running it on the GPU.
 #include <hip/hip_runtime.h>
@@ -146,7 +149,7 @@ struct SharedHead {
     // per step (three in rotation): the maximum over the waves of the wave
     // winner's energy with its last 12 bits replaced by 4095 - its index
     unsigned long long kmax[3];
-    // per step (double-buffered) and wave: the wave winner's coefficient
+    // per step (double-buffered) and wave: the wave winner's value R[u,v]
     double2 sA[2][8];
     int job, blk;
     uint8_t lost[16 * 16];  // lost pixels of the block's B x B core (B <= 16)
@@ -383,7 +386,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     T* Wd = WREG ? Xs : Xs + M * LD;             // weight spectrum [DUP ? M + kWrapRows : M][M] complex
     T* Xw = WREG ? Xs + M * LD : Wd;             // w (M = 32: staged where the weight spectrum goes)
     // coefficient list of the K steps (real parts, imaginary parts, spectrum
-    // indices), written during the steps and read by the synthesis: M = 32
+    // indices; the values are R[u,v], each coefficient is gamma / W0 times
+    // its value), written during the steps and read by the synthesis: M = 32
     // in FP64 over w*s, which the steps no longer read, in FP32 after the
     // weight spectrum, where the buffer (sized for FP64) is free; M = 64
     // after the two staged areas
@@ -425,6 +429,14 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
     if (lane == 0) H.part[wv] = wsum;
     __syncthreads();  // the per-wave sums of w stay in LDS until the steps need W0
+    // gamma / W0 from the per-wave sums (0 for a block without known
+    // pixels), formed where it is needed rather than held in registers
+    auto gain = [&]() {
+        double W0 = H.part[0];
+#pragma unroll
+        for (int q = 1; q < NWG; ++q) W0 += H.part[q];
+        return W0 > 0.0 ? a.gamma / W0 : 0.0;
+    };
 
     // ---- DFT of one input (1: w -> weight spectrum in LDS, 0: w*s -> R in
     // registers) as F X F in two stages of MFMA GEMMs
@@ -481,6 +493,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 
     // stage 2: F T for the wave's tiles; (F T)_re = C T_re + S T_im,
     // (F T)_im = C T_im - S T_re
+    const double g1 = inp == 1 ? gain() : 0.0;
     if (active) {
 #pragma unroll
         for (int ci_ = 0; ci_ < NTI; ++ci_) {
@@ -526,11 +539,13 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                 for (int r = 0; r < 4; ++r) {
                     const int k = ti_o * 16 + (F64 ? (lk + 4 * r) : (4 * lk + r)), l = tj * 16 + li;
                     if (inp == 1) {
-                        Wd[(k * M + l) * 2] = ore[r];
-                        Wd[(k * M + l) * 2 + 1] = oim[r];
+                        // the weight spectrum scaled by gamma / W0
+                        const T sre = (T)(g1 * (double)ore[r]), sim = (T)(g1 * (double)oim[r]);
+                        Wd[(k * M + l) * 2] = sre;
+                        Wd[(k * M + l) * 2 + 1] = sim;
                         if (DUP && k < kWrapRows) {
-                            Wd[((k + M) * M + l) * 2] = ore[r];
-                            Wd[((k + M) * M + l) * 2 + 1] = oim[r];
+                            Wd[((k + M) * M + l) * 2] = sre;
+                            Wd[((k + M) * M + l) * 2 + 1] = sim;
                         }
                     } else {
                         // element order within a lane = increasing spectrum index
@@ -680,6 +695,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         dft_stream(0);  // R
         __syncthreads();  // both staged areas read: the weight spectrum takes them
         if (active) {
+            const double g1 = gain();
             int li = lane & 15, lk = lane >> 4;
 #pragma unroll
             for (int ci_ = 0; ci_ < NTI; ++ci_)
@@ -689,8 +705,9 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
                     for (int r = 0; r < 4; ++r) {
                         const int e = (ci_ * 4 + r) * NTJ + cj;
                         const int k = (ti0 + ci_) * 16 + (F64 ? (lk + 4 * r) : (4 * lk + r)), l = (tj0 + cj) * 16 + li;
-                        Wd[(k * M + l) * 2] = wrr[e];
-                        Wd[(k * M + l) * 2 + 1] = wri[e];
+                        // the weight spectrum scaled by gamma / W0
+                        Wd[(k * M + l) * 2] = (T)(g1 * (double)wrr[e]);
+                        Wd[(k * M + l) * 2 + 1] = (T)(g1 * (double)wri[e]);
                     }
         }
     } else {
@@ -718,7 +735,6 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     // uniform across the block: lets the loop run under scalar control
     const bool live = __builtin_amdgcn_readfirstlane((int)(W0 > 0.0)) != 0;
     const int nsteps = live ? __builtin_amdgcn_readfirstlane(K) : 0;
-    const double g = live ? a.gamma / W0 : 0.0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
     // spectrum index of lane element e = lane_idx + elem_offset(e)
     const int lane_idx = (ti0 * 16 + ROWK * lk) * M + tj0 * 16 + li;
@@ -763,7 +779,9 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
 #pragma unroll
             for (int j = 0; j + st < EPT; j += 2 * st) {
                 const bool take = ev[j + st] > ev[j];
-                ev[j] = take ? ev[j + st] : ev[j];
+                // the larger energy (equal ones are the same value): one
+                // maximum instead of a select per word
+                ev[j] = fmax(ev[j], ev[j + st]);
                 ex[j] = take ? ex[j + st] : ex[j];
                 if constexpr (CARRY) {
                     vr[j] = take ? vr[j + st] : vr[j];
@@ -775,12 +793,14 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         int ix[1] = {lane_idx + elem_offset(ex[0])};
         double car_l, cai_l;
         if constexpr (CARRY) {
-            // the lane's candidate coefficient, formed before the wave
-            // reduction so that it is ready when the winner lane publishes
-            // it (the empty asm keeps it from being sunk into the winner's
-            // branch)
-            car_l = g * (double)vr[0];
-            cai_l = g * (double)vi[0];
+            // the lane's candidate value R (the step's coefficient is
+            // gamma / W0 times it: that factor is in the stored weight
+            // spectrum and in the synthesis), selected and in FP64 before
+            // the wave reduction, so that it is ready when the winner lane
+            // publishes it (the empty asm keeps the tree's value selects out
+            // of the winner's branch)
+            car_l = (double)vr[0];
+            cai_l = (double)vi[0];
             asm volatile("" : "+v"(car_l), "+v"(cai_l));
         }
         // winner lane of the wave: largest energy, then smallest index
@@ -790,8 +810,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             // register selects its value by register index, instead of a
             // select per tree node and element
             const int ew = __builtin_amdgcn_readlane(ex[0], wl);
-            car_l = g * (double)rr[ew];
-            cai_l = g * (double)ri[ew];
+            car_l = (double)rr[ew];
+            cai_l = (double)ri[ew];
         }
         int IDX;
         double ar, ai;
@@ -805,7 +825,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             // orders like its value) with the last 12 bits replaced by
             // 4095 - its index, so equal energies, and energies within 2^-40
             // of each other, go to the smaller index; and it publishes its
-            // coefficient.  Three maxima rotate: the one of the step after
+            // value R[u,v].  Three maxima rotate: the one of the step after
             // this is cleared now (its last readers, two steps back, have all
             // passed the previous barrier).
             static_assert(TM::wave_of_inverts(), "tile owner");
@@ -865,8 +885,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             rr[e] = fma(-tar, wr[e], fma(tai, wi[e], rr[e]));
             ri[e] = fma(-tar, wi[e], fma(-tai, wr[e], ri[e]));
         }
-        // the step's coefficient, recorded off the critical path (read only
-        // after the loop)
+        // the step's value and index, recorded off the critical path (read
+        // only after the loop)
         if (t == 0) {
             car[it] = ar;
             cai[it] = ai;
@@ -890,6 +910,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         for (int it = t; it < nsteps; it += NT) trace[it] = cidx[it];
 
     // ---- synthesis at the block's lost pixels ------------------------------
+    const double g = gain();
     // gs lanes of one wave per pixel, each summing every gs-th step; B*B
     // pixels.  gs stays within a wave (at most 64): the lane sums are
     // combined with shuffles, which do not cross waves.
@@ -909,6 +930,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             }
         }
         for (int off = gs >> 1; off >= 1; off >>= 1) val += __shfl_xor(val, off);
+        val *= g;  // the recorded values are R[u,v]; alpha = gamma R[u,v] / W0
         if (sub == 0 && H.lost[px]) {
             const int y = d.x + py, x = d.y + pxx;
             const int64_t q = (int64_t)y * J.W + x;

@@ -213,7 +213,9 @@ __device__ __forceinline__ int wave_argmax_lane(double e, IndexFn idx_of) {
             bal = __ballot(cand && inv == minv);
         }
     }
-    return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
+    // bal is never empty (some lane holds the maximum): the first set bit
+    // without a zero test
+    return __builtin_amdgcn_readfirstlane(__builtin_ctzll((unsigned long long)bal));
 }
 
 template <class IndexFn>
@@ -226,7 +228,9 @@ __device__ __forceinline__ int wave_argmax_lane(float e, IndexFn idx_of) {
         const unsigned minv = wave_umax(inv);  // with every lane active
         bal = __ballot(cand && inv == minv);
     }
-    return __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)bal) - 1);
+    // bal is never empty (some lane holds the maximum): the first set bit
+    // without a zero test
+    return __builtin_amdgcn_readfirstlane(__builtin_ctzll((unsigned long long)bal));
 }
 
 __device__ __forceinline__ double readlane_t(double v, int l) {
@@ -754,9 +758,12 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const unsigned gather_base =
         ((unsigned)((ti0 * 16 + ROWK * lk) * M * ES) << 16) | (unsigned)((tj0 * 16 + li) * ES);
     constexpr unsigned kGatherMask = ((unsigned)(MASK * M * ES) << 16) | (unsigned)(MASK * ES);
-    // one selection step; P is the parity of the step (double-buffered slots)
-    auto step = [&](const int it, auto parity) {
+    // one selection step; P is the parity of the step (double-buffered
+    // slots), Q the step mod 3 (the maximum it uses) when known at compile
+    // time, else -1
+    auto step = [&](const int it, auto parity, auto rot) {
         constexpr int P = decltype(parity)::value;
+        constexpr int Q = decltype(rot)::value;
         // first-index maximum over the lane's elements (pairwise tree over
         // increasing index: the right operand wins only when strictly larger);
         // the tree carries the element's number (small constants, no
@@ -827,16 +834,19 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             // of each other, go to the smaller index; and it publishes its
             // value R[u,v].  Three maxima rotate: the one of the step after
             // this is cleared now (its last readers, two steps back, have all
-            // passed the previous barrier).
+            // passed the previous barrier, and no wave enters it before this
+            // step's barrier).
             static_assert(TM::wave_of_inverts(), "tile owner");
-            const int ks = it % 3, kn = (it + 1) % 3;
+            const int ks = Q >= 0 ? Q : it % 3, kn = Q >= 0 ? (Q + 1) % 3 : (it + 1) % 3;
             if (lane == wl) {
                 const unsigned long long key =
                     ((unsigned long long)__double_as_longlong((double)lm) & ~0xFFFull) | (unsigned long long)(unsigned)(0xFFF - ix[0]);
                 atomicMax(&H.kmax[ks], key);
                 H.sA[P][wv] = make_double2(car_l, cai_l);
+                // every wave's winner lane clears the same maximum (the
+                // same value written NW times; no condition to evaluate)
+                H.kmax[kn] = 0ull;
             }
-            if (t == 0) H.kmax[kn] = 0ull;
             __syncthreads();  // the maximum and the coefficients visible to every wave
             const unsigned long long km = H.kmax[ks];
             IDX = 0xFFF - (__builtin_amdgcn_readfirstlane((int)(unsigned)km) & 0xFFF);
@@ -897,12 +907,25 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
         if constexpr (NW > 1)
             for (int it = 0; it < nsteps; ++it) __syncthreads();  // the step exchanges of the active waves
     } else {
+        // unrolled by six, so that the slot and maximum offsets are constants
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using IN = std::integral_constant<int, -1>;
         int it = 0;
-        for (; it + 1 < nsteps; it += 2) {
-            step(it, std::integral_constant<int, 0>());
-            step(it + 1, std::integral_constant<int, 1>());
+        for (; it + 6 <= nsteps; it += 6) {
+            step(it, I0(), I0());
+            step(it + 1, I1(), I1());
+            step(it + 2, I0(), I2());
+            step(it + 3, I1(), I0());
+            step(it + 4, I0(), I1());
+            step(it + 5, I1(), I2());
         }
-        if (it < nsteps) step(it, std::integral_constant<int, 0>());
+        for (; it + 1 < nsteps; it += 2) {
+            step(it, I0(), IN());
+            step(it + 1, I1(), IN());
+        }
+        if (it < nsteps) step(it, I0(), IN());
     }
     if (!live && t == 0) atomicAdd((unsigned long long*)a.degenerate, 1ull);
     __syncthreads();  // the coefficient list is complete

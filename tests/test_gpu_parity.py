@@ -116,6 +116,25 @@ def test_lost_input_values_are_not_read():
     assert np.abs(got - ref)[wl.mask.astype(bool)].max() <= TIGHT
 
 
+@pytest.mark.parametrize("waves", [4, 2, 1])
+@pytest.mark.parametrize("K", [1, 3, 5, 7, 13])
+def test_step_counts_around_the_unrolled_loop(K, waves):
+    # the kernel runs the selection steps in groups of six, then in pairs,
+    # then one: counts that end in each of those remainders, and counts
+    # below one group
+    img = synth.synth_image(64, 64, seed=40 + K)
+    mask = synth.mask_blocks_and_pixels(64, 64, 4, 0.2, 0.01, seed=50 + K)
+    _check(img, mask, ((4, 14, K),), block_waves=waves)
+
+
+@pytest.mark.parametrize("K", [5, 13])
+def test_step_counts_around_the_unrolled_loop_64(K):
+    # the same for the eight-wave kernel of 64 x 64 windows
+    img = synth.synth_image(96, 96, seed=60 + K)
+    mask = synth.mask_blocks_and_pixels(96, 96, 8, 0.1, 0.0, seed=70 + K)
+    _check(img, mask, ((8, 28, K),))
+
+
 def test_k_zero_writes_zero_model():
     wl = synth.workload("small")
     got, _, _ = _run(wl.image, wl.mask, ((4, 14, 0),))

@@ -742,6 +742,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
     // spectrum index of lane element e = lane_idx + elem_offset(e)
     const int lane_idx = (ti0 * 16 + ROWK * lk) * M + tj0 * 16 + li;
+    // 4095 - lane_idx: the key's last 12 bits are 4095 - (lane_idx + elem_offset(e))
+    const int lane_key = 0xFFF - lane_idx;
     auto elem_offset = [](int e) {
         const int jr = (e / NTJ) & 3, jci = e / (4 * NTJ), jcj = e % NTJ;
         return (jci * 16 + ROWR * jr) * M + jcj * 16;
@@ -797,7 +799,10 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             }
         }
         const T lm = ev[0];
-        int ix[1] = {lane_idx + elem_offset(ex[0])};
+        // 4095 - the spectrum index of the lane's maximum (the low bits of its
+        // exchange key), and the index itself
+        const int kx = lane_key - elem_offset(ex[0]);
+        int ix[1] = {0xFFF - kx};
         double car_l, cai_l;
         if constexpr (CARRY) {
             // the lane's candidate value R (the step's coefficient is
@@ -840,7 +845,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             const int ks = Q >= 0 ? Q : it % 3, kn = Q >= 0 ? (Q + 1) % 3 : (it + 1) % 3;
             if (lane == wl) {
                 const unsigned long long key =
-                    ((unsigned long long)__double_as_longlong((double)lm) & ~0xFFFull) | (unsigned long long)(unsigned)(0xFFF - ix[0]);
+                    ((unsigned long long)__double_as_longlong((double)lm) & ~0xFFFull) | (unsigned long long)(unsigned)kx;
                 atomicMax(&H.kmax[ks], key);
                 H.sA[P][wv] = make_double2(car_l, cai_l);
                 // every wave's winner lane clears the same maximum (the

@@ -740,8 +740,14 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     const bool live = __builtin_amdgcn_readfirstlane((int)(W0 > 0.0)) != 0;
     const int nsteps = live ? __builtin_amdgcn_readfirstlane(K) : 0;
     int32_t* trace = (J.trace && blk < J.trace_cap) ? J.trace + (int64_t)blk * J.trace_stride : nullptr;
+    // the lane coordinates again, opaque to the compiler: the steps' per-lane
+    // constants below are formed here, per block, instead of being kept in
+    // registers across the DFTs (where they were spilled and reloaded)
+    int sl = lane;
+    asm volatile("" : "+v"(sl));
+    const int sli = sl & 15, slk = sl >> 4;
     // spectrum index of lane element e = lane_idx + elem_offset(e)
-    const int lane_idx = (ti0 * 16 + ROWK * lk) * M + tj0 * 16 + li;
+    const int lane_idx = (ti0 * 16 + ROWK * slk) * M + tj0 * 16 + sli;
     // 4095 - lane_idx: the key's last 12 bits are 4095 - (lane_idx + elem_offset(e))
     const int lane_key = 0xFFF - lane_idx;
     auto elem_offset = [](int e) {
@@ -758,7 +764,7 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
     static_assert(!PACKED || (M - 1) * M * ES < 65536, "packed gather address");
     typedef unsigned short ushort2_v __attribute__((ext_vector_type(2)));
     const unsigned gather_base =
-        ((unsigned)((ti0 * 16 + ROWK * lk) * M * ES) << 16) | (unsigned)((tj0 * 16 + li) * ES);
+        ((unsigned)((ti0 * 16 + ROWK * slk) * M * ES) << 16) | (unsigned)((tj0 * 16 + sli) * ES);
     constexpr unsigned kGatherMask = ((unsigned)(MASK * M * ES) << 16) | (unsigned)(MASK * ES);
     // one selection step; P is the parity of the step (double-buffered
     // slots), Q the step mod 3 (the maximum it uses) when known at compile
@@ -880,8 +886,8 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             for (int ci_ = 0; ci_ < NTI; ++ci_) {
 #pragma unroll
                 for (int cj = 0; cj < NTJ; ++cj) {
-                    const int col = ((tj0 + cj) * 16 + li - v) & MASK;
-                    const int row0 = (ti0 + ci_) * 16 + ROWK * lk - u;
+                    const int col = ((tj0 + cj) * 16 + sli - v) & MASK;
+                    const int row0 = (ti0 + ci_) * 16 + ROWK * slk - u;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int e = (ci_ * 4 + r) * NTJ + cj;

@@ -190,6 +190,15 @@ __device__ __forceinline__ unsigned wave_umax(unsigned v) {
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// More than one lane in a (uniform) ballot: its population count in one
+// scalar instruction (the compiler's form, a 64-bit x & (x - 1), takes four
+// on the step's critical path)
+__device__ __forceinline__ bool several_lanes(uint64_t bal) {
+    int c;
+    asm("s_bcnt1_i32_b64 %0, %1" : "=s"(c) : "s"(bal) : "scc");
+    return c > 1;
+}
+
 // Lane holding the wave's largest non-negative energy; among equal energies
 // the lane whose spectrum index is smallest.  The high words decide in one
 // DPP pass unless several lanes share the largest high word.
@@ -199,12 +208,12 @@ __device__ __forceinline__ int wave_argmax_lane(double e, IndexFn idx_of) {
     const unsigned mhi = wave_umax(hi);
     bool cand = hi == mhi;
     uint64_t bal = __ballot(cand);
-    if (__popcll(bal) > 1) {
+    if (several_lanes(bal)) {
         const unsigned lo = (unsigned)__double2loint(e);
         const unsigned mlo = wave_umax(cand ? lo : 0u);
         cand = cand && lo == mlo;
         bal = __ballot(cand);
-        if (__popcll(bal) > 1) {
+        if (several_lanes(bal)) {
             // exact tie between lanes: the smallest spectrum index among them,
             // as the DPP maximum of its complement (no shuffle addresses to
             // keep in registers)
@@ -223,7 +232,7 @@ __device__ __forceinline__ int wave_argmax_lane(float e, IndexFn idx_of) {
     const unsigned k = __float_as_uint(e);
     const bool cand = k == wave_umax(k);
     uint64_t bal = __ballot(cand);
-    if (__popcll(bal) > 1) {
+    if (several_lanes(bal)) {
         const unsigned inv = cand ? ~(unsigned)idx_of() : 0u;
         const unsigned minv = wave_umax(inv);  // with every lane active
         bal = __ballot(cand && inv == minv);
@@ -1090,13 +1099,14 @@ __global__ void __launch_bounds__(64 * NW, (NW == 4 && !WIDE) ? 5 : (WIDE && PRE
         } else {
             process_block<32, NW, NW, PREC>(a, J, blk, H, buf, tw64);
         }
-        __syncthreads();
+        // process_block ends with a barrier after every wave's stores: thread
+        // 0 publishes the block, then takes the next ticket (the other waves
+        // read the ticket's LDS slots only after the barrier at the top)
         if (t == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(&J.done[blk], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!a.counter) break;
-        __syncthreads();
     }
 }
 

@@ -928,18 +928,22 @@ __device__ void process_block(const LaunchArgs& a, const JobDev& J, int blk, Sha
             for (int it = 0; it < nsteps; ++it) __syncthreads();  // the step exchanges of the active waves
     } else {
         // unrolled by six, so that the slot and maximum offsets are constants
+        // (FP64; the FP32 loops stay unrolled by two: with nine copies of the
+        // step the compiler kept them out of line, their arrays in scratch)
         using I0 = std::integral_constant<int, 0>;
         using I1 = std::integral_constant<int, 1>;
         using I2 = std::integral_constant<int, 2>;
         using IN = std::integral_constant<int, -1>;
         int it = 0;
-        for (; it + 6 <= nsteps; it += 6) {
-            step(it, I0(), I0());
-            step(it + 1, I1(), I1());
-            step(it + 2, I0(), I2());
-            step(it + 3, I1(), I0());
-            step(it + 4, I0(), I1());
-            step(it + 5, I1(), I2());
+        if constexpr (F64) {
+            for (; it + 6 <= nsteps; it += 6) {
+                step(it, I0(), I0());
+                step(it + 1, I1(), I1());
+                step(it + 2, I0(), I2());
+                step(it + 3, I1(), I0());
+                step(it + 4, I0(), I1());
+                step(it + 5, I1(), I2());
+            }
         }
         for (; it + 1 < nsteps; it += 2) {
             step(it, I0(), IN());
